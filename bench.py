@@ -1,0 +1,174 @@
+"""Throughput benchmark of the FE objective + gradient + projected step.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c2]
+
+A step is one pass of the whole hot path over the batch: for every restart and
+every constraint, the literal gather, node products, objective, per-literal
+gradient and scatter, then the projected step of every variable.  The default
+workload is the mixed symmetric-PB instance (n = 2000 variables; 6000 random
+3-clauses, 600 XOR-5 constraints with a random parity bit, 200 "at least 3 of 8"
+cardinality constraints; 1024 restarts; float32 state), synthetic and seeded.
+
+Metric: literal-evaluations per second, R * L * K / t, with t the device time
+of K steps (inputs resident in HBM).  Printed as one JSON line with a roofline
+object for the dominant kernel and the oracle's CPU rate on a bounded sample.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "FE obj+grad literal-evals/sec (% HBM roofline); learned vs random-init sat rate"
+HBM_PEAK_GBS = 8000.0
+PROFILE_DIR = os.path.join(ROOT, "profiles")
+KERNEL_SOURCES = ["paper_2606_06656_amd/csrc/pcls.hip", "paper_2606_06656_amd/csrc/plan.cpp",
+                  "paper_2606_06656_amd/csrc/internal.h"]
+
+
+def workload(name: str):
+    from paper_2606_06656_amd import synth
+    if name == "c2":
+        return synth.c2_mixed(), 1024, 0.1, "mixed_pb_n2000_or3x6000_xor5x600_card3of8x200_R1024"
+    if name == "c3":
+        return synth.c3_long(), 4096, 0.1, "long_support_n20000_m40000_geomk3to256_R4096"
+    if name == "c3long":
+        return synth.c3_forced_long(), 512, 0.1, "forced_long_n20000_k64to256_R512"
+    if name == "c1":
+        return synth.c1_3sat(0), 64, 0.1, "3sat_n50_m213_R64"
+    raise SystemExit(f"unknown workload {name}")
+
+
+def algorithmic_bytes_per_step(n: int, m: int, L: int, R: int) -> int:
+    """4 B x gather + 4 B gradient contribution per literal-evaluation, state read
+    and write per (variable, restart), constraint literal stream and row data."""
+    return 8 * R * L + 8 * R * n + 4 * L + 8 * m
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(workload_key: str, steps: int):
+    """HBM bytes per launch from committed rocprofv3 counter runs, if they were
+    taken on the current kernel source; else None."""
+    path = os.path.join(PROFILE_DIR, f"tile_kernel_{workload_key}_traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    if rec.get("source_sha") != kernel_source_hash():
+        return None
+    per_step = rec.get("hbm_bytes_per_step")
+    return None if per_step is None else float(per_step) * steps
+
+
+def cpu_baseline(inst, lr: float, budget_s: float = 12.0, R_sample: int = 16):
+    """The FP64 oracle (single-threaded C) on a bounded sample of the same
+    workload: R_sample restarts, as many whole steps as fit in about budget_s."""
+    import numpy as np
+
+    from oracle import native as N
+    from paper_2606_06656_amd import synth  # noqa: F401
+
+    op = N.OracleProblem(inst.n, inst.row_ptr, inst.lit, inst.ctype, inst.param, inst.weight)
+    x = N.init_uniform(R_sample, inst.n, 12345)
+    steps = 0
+    t0 = time.perf_counter()
+    while True:
+        res = op.evaluate(x, method=N.AUTO, want_sigma=False)
+        x = N.step(x, res["grad"], lr)
+        steps += 1
+        el = time.perf_counter() - t0
+        if el >= budget_s:
+            break
+    rate = R_sample * inst.L * steps / el
+    return {"value": rate, "unit": "literal-evals/s", "cores": 1, "kind": "oracle",
+            "sample": f"{R_sample} restarts x {steps} steps of the same instance, FP64, single thread, "
+                      f"{el:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=100)
+    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c3long"])
+    ap.add_argument("--tile", type=int, default=0, help="restarts per workgroup (0 = auto)")
+    ap.add_argument("--block", type=int, default=0, help="threads per workgroup (0 = auto)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-budget", type=float, default=12.0)
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (restarts are independent, "
+              "so several GPUs would each run their own share with no per-step exchange).", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_2606_06656_amd import pcls
+
+    inst, R, lr, key = workload(args.workload)
+    prob = pcls.Problem.from_instance(inst, device="cuda:0")
+    if args.tile or args.block:
+        prob.set_launch(args.tile, args.block)
+    X = prob.new_state(R)
+    prob.init_restarts(X, R, 2)
+    stream = torch.cuda.current_stream()
+    if args.warmup > 0:
+        prob.step(X, R, lr, args.warmup)
+    torch.cuda.synchronize()
+
+    start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    start.record(stream)
+    prob.step(X, R, lr, args.steps)  # one launch of the resident kernel runs all K steps
+    end.record(stream)
+    torch.cuda.synchronize()
+    ms = start.elapsed_time(end)
+    t = ms / 1e3
+
+    lit_evals = R * inst.L * args.steps
+    value = lit_evals / t
+    alg_bytes = algorithmic_bytes_per_step(inst.n, inst.m, inst.L, R) * args.steps
+    achieved = alg_bytes / t / 1e9
+    traffic = measured_traffic(key, args.steps)
+    info = prob.info()
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "literal-evals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": key, "n": inst.n, "m": inst.m, "L": inst.L, "restarts": R, "lr": lr,
+                   "tile_restarts": info.tile_restarts, "block_threads": info.block_threads},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "kernel": "tile_kernel", "launch_ms": ms,
+                     "model": "gather model: 8 B per literal-eval + 8 B per (variable, restart) + CSR per step"},
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(inst, lr, args.cpu_budget)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

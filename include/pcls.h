@@ -1,0 +1,170 @@
+/*
+ * pcls - parallel continuous local search for symmetric pseudo-Boolean SAT.
+ *
+ * C ABI of the MI355X (gfx950) library libpcls.so.
+ *
+ * The library evaluates, for many restarts at once, the Walsh-Fourier relaxed
+ * objective F(x) = sum_c w_c FE_c(x) of a formula of symmetric constraints on
+ * the hypercube [-1,1]^n and its gradient, and takes projected gradient steps
+ * x <- clip(x - lr * grad F, -1, 1) (paper: Background, "Satisfaction as
+ * Optimisation"; the FE of one constraint is eq. wft with the coefficients of
+ * eq. wfcoef, Background, "Walsh-Fourier Transformation").
+ *
+ * Conventions.
+ *  - Boolean True is -1 and False is +1.  A literal over variable v has value
+ *    y = s * x_v, s = +1 for a positive literal and -1 for a negated one; a
+ *    positive literal is true at x_v = -1.
+ *  - A symmetric constraint's value at a corner is -1 when it holds and +1
+ *    when it is violated; a corner satisfies the formula iff sum_c FE_c = -m.
+ *  - Restart state X is float32, laid out [n][R_pad] (restart index
+ *    contiguous), R_pad = round_up(R, 64).  Columns r >= R are padding the
+ *    library may read and write.
+ *  - All device pointers are caller-owned (hipMalloc'd or torch tensors).
+ *    Every device operation is enqueued asynchronously on the given HIP
+ *    stream (hipStream_t passed as void*; NULL = the null stream); the host
+ *    pointers passed to pcls_plan are borrowed only for the call.
+ *  - Every function returns a status code and never throws or aborts across
+ *    the ABI; pcls_last_error() describes the last failure on this thread.
+ *  - A planned problem is read-only after pcls_upload: concurrent evaluate /
+ *    step / extract calls on different streams with different X are safe.
+ */
+#ifndef PCLS_H
+#define PCLS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct pcls_problem pcls_problem;
+
+enum {
+  PCLS_OK = 0,
+  PCLS_E_INVALID = 1,      /* malformed input (bad CSR, literal, type, parameter, pointer) */
+  PCLS_E_UNSUPPORTED = 2,  /* constraint longer than 256 literals, or problem too large */
+  PCLS_E_DUPVAR = 3,       /* a variable occurs twice in one constraint */
+  PCLS_E_WORKSPACE = 4,    /* workspace missing or smaller than reported */
+  PCLS_E_HIP = 5           /* a HIP runtime call failed (message holds the HIP error string) */
+};
+
+/* Constraint types (paper: Table 2 and Appendix A). */
+enum {
+  PCLS_OR = 0,      /* at least one literal true                                  */
+  PCLS_XOR = 1,     /* number of true literals = param (mod 2); param 1 = odd parity */
+  PCLS_CARD_GE = 2, /* at least param literals true, 0 <= param <= k               */
+  PCLS_NAE = 3,     /* not all equal: 0 < #true < k                                */
+  PCLS_EO = 4,      /* exactly one true                                            */
+  PCLS_AMO = 5,     /* at most one true                                            */
+  PCLS_EK = 6       /* exactly param true, 0 <= param <= k                         */
+};
+
+/* Planning options (pcls_plan_ex).  Zero-initialised = defaults. */
+typedef struct pcls_plan_options {
+  int32_t force_generic; /* 1: evaluate every constraint through the K-node DFT path
+                            (no one- or two-node product forms); for testing */
+  int32_t reserved[7];
+} pcls_plan_options;
+
+typedef struct pcls_info {
+  int32_t n_vars, n_cons;
+  int64_t n_lits;            /* L = sum of constraint lengths */
+  int32_t max_len;
+  int32_t n_classes;         /* distinct (type, length, param) */
+  int32_t n_segments;
+  int32_t tile_restarts;     /* restarts per workgroup of the resident engine (0 = auto) */
+  int32_t block_threads;     /* threads per workgroup of the resident engine (0 = auto) */
+  size_t workspace_bytes;
+  size_t lds_bytes_per_restart; /* on-chip bytes one restart's state needs */
+} pcls_info;
+
+/*
+ * Validate a formula and plan its evaluation on the host.
+ *   n_vars, n_cons   : n >= 1 variables, m >= 0 constraints.
+ *   row_ptr[m+1]     : host; row_ptr[0] = 0, non-decreasing; constraint c owns
+ *                      lit[row_ptr[c] .. row_ptr[c+1]); every length k >= 1.
+ *   lit[L]           : host; +v / -v, 1 <= v <= n_vars; no variable twice in
+ *                      one constraint (PCLS_E_DUPVAR); k <= 256 (PCLS_E_UNSUPPORTED).
+ *   type[m]          : host; PCLS_OR .. PCLS_EK.
+ *   param[m]         : host; XOR parity in {0,1}; CARD_GE / EK kappa in [0,k];
+ *                      ignored for other types; NULL = all zero.
+ *   weight[m]        : host; finite constraint weights; NULL = all 1.0.
+ * On success *out receives a host plan (free with pcls_destroy) and
+ * *workspace_bytes the size of the device workspace pcls_upload needs.
+ * Computes, per distinct (type, k, param), the spectrum sp_t (eq. wfcoef) and
+ * either its one/two-node product form or the FP64 inverse-DFT weights
+ * chat_m = (1/K) sum_t sp_t omega^-tm, K = k + 1, rounded once to float32.
+ */
+int32_t pcls_plan(int32_t n_vars, int32_t n_cons, const int32_t* row_ptr, const int32_t* lit,
+                  const int8_t* type, const int32_t* param, const float* weight, pcls_problem** out,
+                  size_t* workspace_bytes);
+int32_t pcls_plan_ex(int32_t n_vars, int32_t n_cons, const int32_t* row_ptr, const int32_t* lit,
+                     const int8_t* type, const int32_t* param, const float* weight,
+                     const pcls_plan_options* options, pcls_problem** out, size_t* workspace_bytes);
+
+/* Sizes and launch settings of a plan. */
+int32_t pcls_problem_info(const pcls_problem* p, pcls_info* info);
+
+/*
+ * Copy the plan into caller-owned device memory d_workspace (>= workspace_bytes,
+ * 256-byte aligned), asynchronously on stream, and bind it to the plan.  The
+ * workspace must stay allocated while the plan is used.
+ */
+int32_t pcls_upload(pcls_problem* p, void* d_workspace, size_t bytes, void* hip_stream);
+
+/*
+ * Restart initialisation x[v][r] ~ U[-1,1) (paper: "starting assignments",
+ * Case Studies, "Costas Arrays"; the distribution is this library's choice).
+ * Philox4x32-10 (Salmon et al., SC'11) with counter (r, v, 0, 0) and key
+ * (seed low word, seed high word); the top 24 bits i of the first output word
+ * give x = (i - 2^23) / 2^23.  Padding columns r in [R, R_pad) are set to 0.
+ * d_x: device [n][R_pad] float32.
+ */
+int32_t pcls_init_restarts(const pcls_problem* p, int32_t R, uint64_t seed, float* d_x, void* hip_stream);
+
+/*
+ * Objective and gradient at X (Background, "Satisfaction as Optimisation").
+ *   d_x    : device [n][R_pad] float32, read only.
+ *   d_obj  : device [R] float32, F_r = sum_c w_c FE_c(x_r).
+ *   d_grad : device [n][R_pad] float32 (padding columns written too) or NULL.
+ */
+int32_t pcls_evaluate(const pcls_problem* p, int32_t R, const float* d_x, float* d_obj, float* d_grad,
+                      void* hip_stream);
+
+/*
+ * n_steps >= 0 projected gradient steps x <- min(1, max(-1, x - lr * grad F(x)))
+ * in place on d_x ([n][R_pad] float32).  If d_obj_trace is not NULL it receives
+ * [n_steps][R] float32: entry (s, r) is F at x_s, before step s.
+ */
+int32_t pcls_step(const pcls_problem* p, int32_t R, float* d_x, float lr, int32_t n_steps,
+                  float* d_obj_trace, void* hip_stream);
+
+/*
+ * Round X to corners and count violated constraints exactly.
+ *   d_assign : device [R][n] int8 or NULL; -1 (True) where x < 0, else +1
+ *              (False; -0.0 and +0.0 both give False).
+ *   d_unsat  : device [R] int32, number of constraints violated by the corner.
+ *   d_best   : device [1] int32 or NULL: restart with the fewest violations,
+ *              ties to the lowest index.
+ */
+int32_t pcls_extract(const pcls_problem* p, int32_t R, const float* d_x, int8_t* d_assign,
+                     int32_t* d_unsat, int32_t* d_best, void* hip_stream);
+
+/*
+ * Launch settings of the resident engine: restarts per workgroup (power of
+ * two, 1..64) and threads per workgroup (256, 512 or 1024); 0 = automatic.
+ * PCLS_E_UNSUPPORTED if the setting does not fit the device's on-chip memory.
+ */
+int32_t pcls_set_launch(pcls_problem* p, int32_t tile_restarts, int32_t block_threads);
+
+/* Free the host plan; never frees caller memory. */
+int32_t pcls_destroy(pcls_problem* p);
+
+/* Thread-local description of the last error; valid until the next call. */
+const char* pcls_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PCLS_H */

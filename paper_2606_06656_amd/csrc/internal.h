@@ -1,0 +1,94 @@
+// Internal layout shared by the host planner and the gfx950 kernels.
+//
+// A planned problem is one contiguous device image (caller-owned workspace).
+// Constraints are reordered into segments; each segment holds constraints of
+// one evaluation kind and one length bucket, so a wavefront runs one code path.
+#pragma once
+#include <cstddef>
+#include <cstdint>
+
+namespace pcls {
+
+// Evaluation kinds.  Every kind evaluates FE = sum_t sp_t Pr[T = t] (T = number
+// of true literals under independent literals of mean y) through products of
+// per-literal factors (alpha + beta * y) at a set of nodes:
+//   PROD1 - one real node (sp constant except at t = 0, t = k, or alternating):
+//           FE = c0 + c1 * prod_i (a + b y_i)
+//   PROD2 - two real nodes (sp constant on 1..k-1):
+//           FE = c0 + c1 * prod_i (1+y_i)/2 + c2 * prod_i (1-y_i)/2
+//   DFT   - the K = k+1 complex roots of unity: FE = sum_m chat_m prod_i(alpha_m + beta_m y_i)
+//   CONST - sp constant: FE = c0, no literal work
+enum Kind : int32_t { KIND_PROD1 = 0, KIND_PROD2 = 1, KIND_DFT = 2, KIND_CONST = 3 };
+
+// Length buckets of the segment kernels: literals per constraint padded to KMAX,
+// processed by groups of G lanes holding J = KMAX / G literals each.
+constexpr int kNumBuckets = 13;
+constexpr int kBucketKmax[kNumBuckets] = {1, 2, 3, 4, 5, 6, 7, 8, 16, 32, 64, 128, 256};
+constexpr int kMaxK = 256;
+
+// Lanes per (constraint, restart) pair: one lane holds up to 16 literals of a
+// product kind or 8 of the DFT kind (register budget at 4 waves per SIMD);
+// longer constraints spread over G lanes of 8 literals each.
+constexpr int group_size(int kind, int kmax) {
+  return kind == KIND_DFT ? (kmax <= 8 ? 1 : kmax / 8) : (kmax <= 16 ? 1 : kmax / 8);
+}
+
+inline int bucket_of(int k) {
+  for (int b = 0; b < kNumBuckets; ++b)
+    if (k <= kBucketKmax[b]) return b;
+  return -1;
+}
+
+struct Segment {
+  int32_t kind;       // Kind
+  int32_t bucket;     // index into kBucketKmax
+  int32_t c_begin;    // first constraint (planned order)
+  int32_t c_count;    // constraints in the segment
+  int32_t lit_base;   // offset of the segment's transposed literal block
+  int32_t k_fixed;    // > 0 when every constraint has this length
+  int32_t cls_fixed;  // >= 0 when every constraint has this class
+  int32_t m_max;      // DFT: largest number of complex nodes over the segment
+};
+
+// Per constraint class (type, k, param).
+struct ClassRec {
+  int32_t kind;
+  int32_t k;
+  int32_t n_nodes;   // DFT: complex nodes m = 1..n_nodes
+  int32_t node_off;  // DFT: offset into the node table (entries)
+  int32_t nyquist;   // DFT: 1 when K = k + 1 is even (real node at omega = -1)
+  int32_t sp_off;    // offset of sp[0..k] (int8) in the spectrum table
+  float a, b;        // PROD1 node factor a + b y
+  float c1, c2;      // PROD1 / PROD2 product weights; DFT: c1 = chat_{K/2} (Nyquist weight)
+  float c0;          // constant term (folded into the per-problem constant on device)
+  float pad;
+};
+
+// DFT node m of a class: factor alpha + beta y, weight 2*chat_m for the value
+// and 2*chat_m*beta_m for the gradient (the 2 covers the conjugate node K - m).
+struct NodeRec {
+  float ar, ai, br, bi;
+  float wr, wi, gr, gi;
+};
+
+// Device view of a planned problem (passed by value to kernels).
+struct ProblemDev {
+  int32_t n, m, L;
+  int32_t n_segments;
+  int32_t n_classes;
+  float f_const;                 // sum_c w_c c0_c
+  const Segment* segments;
+  const ClassRec* classes;
+  const NodeRec* nodes;
+  const int8_t* sp;              // spectra
+  const int32_t* litT;           // per segment: [KMAX][c_count] literal codes (v << 1 | neg)
+  const int32_t* c_k;            // per constraint length (planned order)
+  const int32_t* c_cls;          // per constraint class
+  const float* c_w;              // per constraint weight
+  const int32_t* row_ptr;        // planned-order CSR (extract / streaming engine)
+  const int32_t* lit;            // planned-order literal codes
+  int32_t unit_weights;          // all weights 1.0
+  int32_t max_k;
+};
+
+}  // namespace pcls

@@ -1,0 +1,773 @@
+// gfx950 kernels and C-ABI entry points of libpcls.
+//
+// Resident engine: one workgroup owns a tile of T restarts of one problem and
+// keeps that tile's state x[n][T] and gradient g[n][T] in LDS for all steps of
+// a launch.  Per step every constraint is evaluated for the T restarts
+// (literal gather from LDS, node products, division-free prefix/suffix
+// gradient, LDS atomic scatter), then x <- clip(x - lr g, -1, 1) in LDS.  HBM
+// sees x once in and once out per launch plus the constraint stream.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+
+#include "plan.h"
+
+using namespace pcls;
+
+namespace pcls {
+const char* last_error();
+}
+
+namespace {
+
+constexpr int kWave = 64;
+
+struct cf {
+  float r, i;
+};
+
+__device__ __forceinline__ cf cmul(cf a, cf b) {
+  return {fmaf(a.r, b.r, -a.i * b.i), fmaf(a.r, b.i, a.i * b.r)};
+}
+
+template <int G>
+struct Log2 {
+  static constexpr int v = 1 + Log2<G / 2>::v;
+};
+template <>
+struct Log2<1> {
+  static constexpr int v = 0;
+};
+
+// ---------------------------------------------------------------- group scans
+// The G lanes of one (constraint, restart) pair sit at stride T in the wave:
+// lane = base + lig * T.  Exclusive prefix / suffix products of one value per
+// lane (Hillis-Steele over log2 G shuffle steps).
+template <int G>
+__device__ __forceinline__ float grp_prefix(float v, int lig, int T) {
+  if constexpr (G == 1) {
+    return 1.f;
+  } else {
+    float inc = v;
+#pragma unroll
+    for (int d = 1; d < G; d <<= 1) {
+      float o = __shfl_up(inc, d * T);
+      if (lig >= d) inc *= o;
+    }
+    float ex = __shfl_up(inc, T);
+    return lig == 0 ? 1.f : ex;
+  }
+}
+
+template <int G>
+__device__ __forceinline__ float grp_suffix(float v, int lig, int T) {
+  if constexpr (G == 1) {
+    return 1.f;
+  } else {
+    float inc = v;
+#pragma unroll
+    for (int d = 1; d < G; d <<= 1) {
+      float o = __shfl_down(inc, d * T);
+      if (lig + d < G) inc *= o;
+    }
+    float ex = __shfl_down(inc, T);
+    return lig == G - 1 ? 1.f : ex;
+  }
+}
+
+template <int G>
+__device__ __forceinline__ cf grp_prefix_c(cf v, int lig, int T) {
+  if constexpr (G == 1) {
+    return {1.f, 0.f};
+  } else {
+    cf inc = v;
+#pragma unroll
+    for (int d = 1; d < G; d <<= 1) {
+      cf o{__shfl_up(inc.r, d * T), __shfl_up(inc.i, d * T)};
+      if (lig >= d) inc = cmul(o, inc);
+    }
+    cf ex{__shfl_up(inc.r, T), __shfl_up(inc.i, T)};
+    return lig == 0 ? cf{1.f, 0.f} : ex;
+  }
+}
+
+template <int G>
+__device__ __forceinline__ cf grp_suffix_c(cf v, int lig, int T) {
+  if constexpr (G == 1) {
+    return {1.f, 0.f};
+  } else {
+    cf inc = v;
+#pragma unroll
+    for (int d = 1; d < G; d <<= 1) {
+      cf o{__shfl_down(inc.r, d * T), __shfl_down(inc.i, d * T)};
+      if (lig + d < G) inc = cmul(inc, o);
+    }
+    cf ex{__shfl_down(inc.r, T), __shfl_down(inc.i, T)};
+    return lig == G - 1 ? cf{1.f, 0.f} : ex;
+  }
+}
+
+// ------------------------------------------------------ one constraint, one restart
+// Literal i of the pair's constraint is handled by group lane i / J, slot i % J.
+
+struct PairCtx {
+  int k, cls;
+  float w;
+};
+
+__device__ __forceinline__ PairCtx pair_ctx(const ProblemDev& P, const Segment& S, int c) {
+  PairCtx q;
+  q.k = S.k_fixed > 0 ? S.k_fixed : P.c_k[c];
+  q.cls = S.cls_fixed >= 0 ? S.cls_fixed : P.c_cls[c];
+  q.w = P.unit_weights ? 1.f : P.c_w[c];
+  return q;
+}
+
+// Product kinds: FE - c0 = c1 prod (a + b y) [+ c2 prod (1 - y)/2];
+// dFE/dy_i = c1 b prod_{j != i} (a + b y_j) [- c2/2 prod_{j != i} (1 - y_j)/2].
+template <int NN, int KMAX, int G>
+__device__ __forceinline__ void prod_pair(const ProblemDev& P, const Segment& S, int c_local, int lig, int t,
+                                          int logT, const float* xs, float* gs, float& facc) {
+  constexpr int J = KMAX / G;
+  constexpr bool kExact = KMAX <= 8;  // buckets up to 8 hold a single length
+  const int T = 1 << logT;
+  const PairCtx q = pair_ctx(P, S, S.c_begin + c_local);
+  const ClassRec& C = P.classes[q.cls];
+  const float a1 = C.a, b1 = C.b, c1 = C.c1, c2 = C.c2;
+  const int32_t* lp = P.litT + S.lit_base + c_local;
+
+  int addr[J];
+  float f1[J], f2[J];
+#pragma unroll
+  for (int j = 0; j < J; ++j) {
+    const int i = lig * J + j;
+    addr[j] = -1;
+    f1[j] = 1.f;
+    f2[j] = 1.f;
+    if (kExact || i < q.k) {
+      const int code = lp[i * S.c_count];
+      const int a = ((code >> 1) << logT) + t;
+      const float x = xs[a];
+      const float y = (code & 1) ? -x : x;
+      addr[j] = (a << 1) | (code & 1);
+      f1[j] = fmaf(b1, y, a1);
+      if constexpr (NN == 2) f2[j] = fmaf(-0.5f, y, 0.5f);
+    }
+  }
+  float pre1[J], pre2[J];
+  float run1 = 1.f, run2 = 1.f;
+#pragma unroll
+  for (int j = 0; j < J; ++j) {
+    pre1[j] = run1;
+    run1 *= f1[j];
+    if constexpr (NN == 2) {
+      pre2[j] = run2;
+      run2 *= f2[j];
+    }
+  }
+  const float xp1 = grp_prefix<G>(run1, lig, T), xq1 = grp_suffix<G>(run1, lig, T);
+  float xp2 = 1.f, xq2 = 1.f;
+  if constexpr (NN == 2) {
+    xp2 = grp_prefix<G>(run2, lig, T);
+    xq2 = grp_suffix<G>(run2, lig, T);
+  }
+  if (lig == 0) {
+    float fe = c1 * (run1 * xq1);
+    if constexpr (NN == 2) fe = fmaf(c2, run2 * xq2, fe);
+    facc = fmaf(q.w, fe, facc);
+  }
+  const float s1 = c1 * b1 * q.w * xp1;
+  const float s2 = -0.5f * c2 * q.w * xp2;
+  float suf1 = xq1, suf2 = xq2;
+#pragma unroll
+  for (int j = J - 1; j >= 0; --j) {
+    float g = s1 * pre1[j] * suf1;
+    suf1 *= f1[j];
+    if constexpr (NN == 2) {
+      g = fmaf(s2 * pre2[j], suf2, g);
+      suf2 *= f2[j];
+    }
+    if (addr[j] >= 0) atomicAdd(&gs[addr[j] >> 1], (addr[j] & 1) ? -g : g);
+  }
+}
+
+// Generic kind: FE - chat_0 = sum_{m=1}^{M} Re(2 chat_m Q_m) [+ chat_{K/2} prod y];
+// dFE/dy_i = sum_m Re(2 chat_m beta_m prod_{j != i}(alpha_m + beta_m y_j)) [+ chat_{K/2} prod_{j != i} y_j].
+template <int KMAX, int G>
+__device__ __forceinline__ void dft_pair(const ProblemDev& P, const Segment& S, int c_local, int lig, int t,
+                                         int logT, const float* xs, float* gs, float& facc) {
+  constexpr int J = KMAX / G;
+  constexpr bool kExact = KMAX <= 8;
+  const int T = 1 << logT;
+  const PairCtx q = pair_ctx(P, S, S.c_begin + c_local);
+  const ClassRec& C = P.classes[q.cls];
+  const int32_t* lp = P.litT + S.lit_base + c_local;
+
+  int addr[J];
+  float y[J], g[J];
+#pragma unroll
+  for (int j = 0; j < J; ++j) {
+    const int i = lig * J + j;
+    addr[j] = -1;
+    y[j] = 1.f;
+    g[j] = 0.f;
+    if (kExact || i < q.k) {
+      const int code = lp[i * S.c_count];
+      const int a = ((code >> 1) << logT) + t;
+      const float x = xs[a];
+      y[j] = (code & 1) ? -x : x;
+      addr[j] = (a << 1) | (code & 1);
+    }
+  }
+  float fe = 0.f;
+  if (C.nyquist) {  // real node omega^(K/2) = -1: factor y, padded slots hold y = 1
+    const float cn = C.c1;
+    float pre[J];
+    float run = 1.f;
+#pragma unroll
+    for (int j = 0; j < J; ++j) {
+      pre[j] = run;
+      run *= y[j];
+    }
+    const float xp = grp_prefix<G>(run, lig, T), xq = grp_suffix<G>(run, lig, T);
+    fe = cn * (run * xq);
+    const float sc = cn * xp;
+    float suf = xq;
+#pragma unroll
+    for (int j = J - 1; j >= 0; --j) {
+      g[j] = sc * pre[j] * suf;
+      suf *= y[j];
+    }
+  }
+  const NodeRec* nd = P.nodes + C.node_off;
+  const int nn = C.n_nodes;
+  for (int mm = 0; mm < S.m_max; ++mm) {
+    if (mm < nn) {
+      const NodeRec N = nd[mm];
+      cf pre[J];
+      cf run{1.f, 0.f};
+#pragma unroll
+      for (int j = 0; j < J; ++j) {
+        pre[j] = run;
+        const bool ok = kExact || addr[j] >= 0;
+        const cf f = ok ? cf{fmaf(N.br, y[j], N.ar), fmaf(N.bi, y[j], N.ai)} : cf{1.f, 0.f};
+        run = cmul(run, f);
+      }
+      const cf xp = grp_prefix_c<G>(run, lig, T);
+      const cf xq = grp_suffix_c<G>(run, lig, T);
+      const cf tot = cmul(run, xq);
+      fe = fmaf(N.wr, tot.r, fmaf(-N.wi, tot.i, fe));
+      // gradient weight with the group prefix folded in
+      const cf gw = cmul(cf{N.gr, N.gi}, xp);
+      cf suf = xq;
+#pragma unroll
+      for (int j = J - 1; j >= 0; --j) {
+        const cf pz = cmul(pre[j], suf);
+        g[j] = fmaf(gw.r, pz.r, fmaf(-gw.i, pz.i, g[j]));  // Re(gw * pz)
+        const bool ok = kExact || addr[j] >= 0;
+        const cf f = ok ? cf{fmaf(N.br, y[j], N.ar), fmaf(N.bi, y[j], N.ai)} : cf{1.f, 0.f};
+        suf = cmul(suf, f);
+      }
+    }
+  }
+  if (lig == 0) facc = fmaf(q.w, fe, facc);
+#pragma unroll
+  for (int j = 0; j < J; ++j) {
+    if (addr[j] >= 0) {
+      const float gv = q.w * g[j];
+      atomicAdd(&gs[addr[j] >> 1], (addr[j] & 1) ? -gv : gv);
+    }
+  }
+}
+
+template <int KIND, int KMAX>
+__device__ __forceinline__ void run_segment(const ProblemDev& P, const Segment& S, const float* xs, float* gs,
+                                            float& facc, int tid, int nth, int logT) {
+  constexpr int G = group_size(KIND, KMAX);
+  constexpr int LG = Log2<G>::v;
+  // keep the lane-index arithmetic inside the segment: hoisting it out of the
+  // step loop for every instantiation at once exhausts the register budget
+  asm volatile("" : "+v"(tid));
+  const int t = tid & ((1 << logT) - 1);
+  const int lig = (tid >> logT) & (G - 1);
+  const int slot = tid >> (logT + LG);
+  const int nslots = nth >> (logT + LG);
+  for (int cl = slot; cl < S.c_count; cl += nslots) {
+    if constexpr (KIND == KIND_DFT)
+      dft_pair<KMAX, G>(P, S, cl, lig, t, logT, xs, gs, facc);
+    else
+      prod_pair<KIND == KIND_PROD2 ? 2 : 1, KMAX, G>(P, S, cl, lig, t, logT, xs, gs, facc);
+  }
+}
+
+#define PCLS_BUCKET_CASES(KIND, X) \
+  X(KIND, 0, 1)                    \
+  X(KIND, 1, 2)                    \
+  X(KIND, 2, 3)                    \
+  X(KIND, 3, 4)                    \
+  X(KIND, 4, 5)                    \
+  X(KIND, 5, 6)                    \
+  X(KIND, 6, 7)                    \
+  X(KIND, 7, 8)                    \
+  X(KIND, 8, 16)                   \
+  X(KIND, 9, 32)                   \
+  X(KIND, 10, 64)                  \
+  X(KIND, 11, 128)                 \
+  X(KIND, 12, 256)
+
+#define PCLS_CASE(KIND, B, KMAX) \
+  case (KIND)*kNumBuckets + (B): \
+    run_segment<KIND, KMAX>(P, S, xs, gs, facc, tid, nth, logT); \
+    break;
+
+__device__ __forceinline__ void run_any_segment(const ProblemDev& P, const Segment& S, const float* xs, float* gs,
+                                             float& facc, int tid, int nth, int logT) {
+  switch (S.kind * kNumBuckets + S.bucket) {
+    PCLS_BUCKET_CASES(KIND_PROD1, PCLS_CASE)
+    PCLS_BUCKET_CASES(KIND_PROD2, PCLS_CASE)
+    PCLS_BUCKET_CASES(KIND_DFT, PCLS_CASE)
+    default:
+      break;
+  }
+}
+
+// One workgroup per tile of T = 2^logT restarts; all n_steps steps in LDS.
+// Evaluate mode (obj_out != NULL): one evaluation, writes F and optionally G.
+__global__ void __launch_bounds__(1024) tile_kernel(ProblemDev P, float* __restrict__ X, int R, int ldx,
+                                                    int logT, float lr, int n_steps, float* __restrict__ trace,
+                                                    float* __restrict__ obj_out, float* __restrict__ g_out) {
+  extern __shared__ float lds[];
+  const int T = 1 << logT;
+  const int NT = P.n << logT;
+  float* xs = lds;
+  float* gs = lds + NT;
+  float* Fs = gs + NT;
+  const int tid = threadIdx.x, nth = blockDim.x;
+  const int r0 = blockIdx.x * T;
+  const int t = tid & (T - 1);
+  const bool eval = obj_out != nullptr;
+
+  for (int i = tid; i < NT; i += nth) {
+    const int v = i >> logT, tt = i & (T - 1);
+    xs[i] = X[(size_t)v * ldx + r0 + tt];
+    gs[i] = 0.f;
+  }
+  if (tid < T) Fs[tid] = 0.f;
+  __syncthreads();
+
+  for (int s = 0; s < n_steps; ++s) {
+    float facc = 0.f;
+    for (int sg = 0; sg < P.n_segments; ++sg) {
+      const Segment S = P.segments[sg];
+      run_any_segment(P, S, xs, gs, facc, tid, nth, logT);
+    }
+    // lanes with equal (lane mod T) hold the same restart
+    for (int o = T; o < kWave; o <<= 1) facc += __shfl_xor(facc, o);
+    if ((tid & (kWave - 1)) < T) atomicAdd(&Fs[t], facc);
+    __syncthreads();
+    if (tid < T) {
+      const float F = Fs[tid] + P.f_const;
+      Fs[tid] = 0.f;
+      const int r = r0 + tid;
+      if (r < R) {
+        if (trace) trace[(size_t)s * R + r] = F;
+        if (eval) obj_out[r] = F;
+      }
+    }
+    if (eval) {
+      if (g_out) {
+        for (int i = tid; i < NT; i += nth) {
+          const int v = i >> logT, tt = i & (T - 1);
+          g_out[(size_t)v * ldx + r0 + tt] = gs[i];
+        }
+      }
+    } else {
+      for (int i = tid; i < NT; i += nth) {
+        const float xn = fmaf(-lr, gs[i], xs[i]);
+        xs[i] = fminf(1.f, fmaxf(-1.f, xn));
+        gs[i] = 0.f;
+      }
+    }
+    __syncthreads();
+  }
+  if (!eval) {
+    for (int i = tid; i < NT; i += nth) {
+      const int v = i >> logT, tt = i & (T - 1);
+      X[(size_t)v * ldx + r0 + tt] = xs[i];
+    }
+  }
+}
+
+// ------------------------------------------------------------------- init
+
+__device__ __forceinline__ uint32_t philox_first_word(uint32_t c0, uint32_t c1, uint32_t k0, uint32_t k1) {
+  uint32_t c2 = 0u, c3 = 0u;
+#pragma unroll
+  for (int round = 0; round < 10; ++round) {
+    const uint32_t hi0 = __umulhi(0xD2511F53u, c0), lo0 = 0xD2511F53u * c0;
+    const uint32_t hi1 = __umulhi(0xCD9E8D57u, c2), lo1 = 0xCD9E8D57u * c2;
+    const uint32_t n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
+    c1 = lo1;
+    c3 = lo0;
+    c0 = n0;
+    c2 = n2;
+    k0 += 0x9E3779B9u;
+    k1 += 0xBB67AE85u;
+  }
+  return c0;
+}
+
+__global__ void init_kernel(float* __restrict__ X, int n, int R, int ldx, uint32_t k0, uint32_t k1) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  const int v = blockIdx.y;
+  if (r >= ldx || v >= n) return;
+  float x = 0.f;
+  if (r < R) {
+    const uint32_t o = philox_first_word((uint32_t)r, (uint32_t)v, k0, k1);
+    x = (float)((int32_t)(o >> 8) - 8388608) * (1.0f / 8388608.0f);
+  }
+  X[(size_t)v * ldx + r] = x;
+}
+
+// ---------------------------------------------------------------- extract
+
+__global__ void fill_i32_kernel(int32_t* p, int32_t v, int count) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < count) p[i] = v;
+}
+
+// lane = restart; each block row covers a chunk of constraints
+__global__ void extract_count_kernel(ProblemDev P, const float* __restrict__ X, int R, int ldx,
+                                     int32_t* __restrict__ unsat, int chunk) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  const int c0 = blockIdx.y * chunk;
+  const int c1 = min(P.m, c0 + chunk);
+  if (r >= R) return;
+  int cnt = 0;
+  for (int c = c0; c < c1; ++c) {
+    const int b = P.row_ptr[c], e = P.row_ptr[c + 1];
+    int ntrue = 0;
+    for (int i = b; i < e; ++i) {
+      const int code = P.lit[i];
+      const bool var_true = X[(size_t)(code >> 1) * ldx + r] < 0.f;
+      ntrue += (var_true != (bool)(code & 1)) ? 1 : 0;
+    }
+    const ClassRec& C = P.classes[P.c_cls[c]];
+    cnt += P.sp[C.sp_off + ntrue] > 0 ? 1 : 0;
+  }
+  if (cnt) atomicAdd(&unsat[r], cnt);
+}
+
+// 64 x 64 tile transpose: X[v][r] -> assign[r][v]
+__global__ void extract_assign_kernel(const float* __restrict__ X, int n, int R, int ldx, int8_t* __restrict__ assign) {
+  __shared__ int8_t tile[64][65];
+  const int r0 = blockIdx.x * 64, v0 = blockIdx.y * 64;
+  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;  // 256 threads: 4 rows per pass
+  for (int q = ty; q < 64; q += 4) {
+    const int v = v0 + q, r = r0 + tx;
+    int8_t z = 1;
+    if (v < n && r < R) z = X[(size_t)v * ldx + r] < 0.f ? (int8_t)-1 : (int8_t)1;
+    tile[q][tx] = z;
+  }
+  __syncthreads();
+  for (int q = ty; q < 64; q += 4) {
+    const int r = r0 + q, v = v0 + tx;
+    if (r < R && v < n) assign[(size_t)r * n + v] = tile[tx][q];
+  }
+}
+
+__global__ void extract_best_kernel(const int32_t* __restrict__ unsat, int R, int32_t* __restrict__ best) {
+  __shared__ unsigned long long red[1024];
+  unsigned long long key = ~0ull;
+  for (int r = threadIdx.x; r < R; r += blockDim.x) {
+    const unsigned long long kk = ((unsigned long long)(uint32_t)unsat[r] << 32) | (uint32_t)r;
+    key = kk < key ? kk : key;
+  }
+  red[threadIdx.x] = key;
+  __syncthreads();
+  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) {
+      const unsigned long long o = red[threadIdx.x + s];
+      if (o < red[threadIdx.x]) red[threadIdx.x] = o;
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) best[0] = R > 0 ? (int32_t)(red[0] & 0xffffffffu) : -1;
+}
+
+// ------------------------------------------------------------------ host side
+
+int32_t hip_fail(hipError_t e, const char* what) {
+  return set_error(PCLS_E_HIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+#define PCLS_HIP(call, what)                 \
+  do {                                       \
+    hipError_t _e = (call);                  \
+    if (_e != hipSuccess) return hip_fail(_e, what); \
+  } while (0)
+
+int round_up64(int R) { return (R + 63) / 64 * 64; }
+
+struct DeviceLimits {
+  int lds_max = 0;
+  int n_cu = 0;
+  bool lds_attr_set = false;
+};
+
+std::mutex g_dev_mu;
+DeviceLimits g_dev[64];
+
+int32_t device_limits(DeviceLimits& out) {
+  int dev = 0;
+  PCLS_HIP(hipGetDevice(&dev), "hipGetDevice");
+  if (dev < 0 || dev >= 64) return set_error(PCLS_E_HIP, "device index %d out of range", dev);
+  std::lock_guard<std::mutex> lk(g_dev_mu);
+  DeviceLimits& d = g_dev[dev];
+  if (d.lds_max == 0) {
+    int v = 0;
+    PCLS_HIP(hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev), "hipDeviceGetAttribute");
+    d.lds_max = v;
+    PCLS_HIP(hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev), "hipDeviceGetAttribute");
+    d.n_cu = v;
+  }
+  if (!d.lds_attr_set) {
+    PCLS_HIP(hipFuncSetAttribute((const void*)tile_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, d.lds_max),
+             "hipFuncSetAttribute");
+    d.lds_attr_set = true;
+  }
+  out = d;
+  return PCLS_OK;
+}
+
+size_t tile_lds_bytes(int n, int T) { return ((size_t)2 * n * T + (size_t)T) * sizeof(float); }
+
+struct Launch {
+  int logT;
+  int block;
+  size_t lds;
+};
+
+// Restarts per workgroup: largest power of two whose state fits in LDS, at
+// most 64 / G_max (a lane group must stay inside one wave), and small enough
+// to give every compute unit at least two tiles when R allows it.
+int32_t choose_launch(const pcls_problem* p, int R, Launch& L) {
+  DeviceLimits lim;
+  int32_t st = device_limits(lim);
+  if (st != PCLS_OK) return st;
+  const int R_pad = round_up64(R);
+  const int tmax_group = kWave / std::max(1, p->max_group);
+  int T;
+  if (p->tile_restarts > 0) {
+    T = p->tile_restarts;
+  } else {
+    T = 1;
+    const int want_tiles = 2 * std::max(1, lim.n_cu);
+    while (T * 2 <= tmax_group && tile_lds_bytes(p->n, T * 2) <= (size_t)lim.lds_max && R_pad / (T * 2) >= want_tiles)
+      T *= 2;
+  }
+  if (T < 1 || T > 64 || (T & (T - 1)))
+    return set_error(PCLS_E_INVALID, "tile_restarts %d must be a power of two in [1, 64]", T);
+  if (T > tmax_group)
+    return set_error(PCLS_E_UNSUPPORTED, "tile_restarts %d too large for constraints of %d literals", T, p->max_k);
+  const size_t lds = tile_lds_bytes(p->n, T);
+  if (lds > (size_t)lim.lds_max)
+    return set_error(PCLS_E_UNSUPPORTED,
+                     "state of %d variables x %d restarts needs %zu bytes of LDS (device limit %d)", p->n, T, lds,
+                     lim.lds_max);
+  int block = p->block_threads;
+  if (block <= 0) block = lds > (size_t)lim.lds_max / 2 ? 1024 : 512;
+  if (block != 256 && block != 512 && block != 1024)
+    return set_error(PCLS_E_INVALID, "block_threads %d must be 256, 512 or 1024", block);
+  L.logT = 0;
+  while ((1 << L.logT) < T) ++L.logT;
+  L.block = block;
+  L.lds = lds;
+  return PCLS_OK;
+}
+
+int32_t check_bound(const pcls_problem* p) {
+  if (!p) return set_error(PCLS_E_INVALID, "problem handle is NULL");
+  if (!p->d_ws) return set_error(PCLS_E_WORKSPACE, "problem has no device workspace (call pcls_upload)");
+  return PCLS_OK;
+}
+
+int32_t launch_tile(const pcls_problem* p, int R, float* d_x, float lr, int n_steps, float* trace, float* obj,
+                    float* grad, hipStream_t stream) {
+  Launch L;
+  int32_t st = choose_launch(p, R, L);
+  if (st != PCLS_OK) return st;
+  const int R_pad = round_up64(R);
+  const int tiles = R_pad >> L.logT;
+  hipLaunchKernelGGL(tile_kernel, dim3(tiles), dim3(L.block), L.lds, stream, p->dev, d_x, R, R_pad, L.logT, lr,
+                     n_steps, trace, obj, grad);
+  PCLS_HIP(hipGetLastError(), "tile_kernel launch");
+  return PCLS_OK;
+}
+
+}  // namespace
+
+// ======================================================================= C ABI
+
+extern "C" {
+
+int32_t pcls_plan(int32_t n_vars, int32_t n_cons, const int32_t* row_ptr, const int32_t* lit, const int8_t* type,
+                  const int32_t* param, const float* weight, pcls_problem** out, size_t* workspace_bytes) {
+  return build_plan(n_vars, n_cons, row_ptr, lit, type, param, weight, nullptr, out, workspace_bytes);
+}
+
+int32_t pcls_plan_ex(int32_t n_vars, int32_t n_cons, const int32_t* row_ptr, const int32_t* lit,
+                     const int8_t* type, const int32_t* param, const float* weight,
+                     const pcls_plan_options* options, pcls_problem** out, size_t* workspace_bytes) {
+  return build_plan(n_vars, n_cons, row_ptr, lit, type, param, weight, options, out, workspace_bytes);
+}
+
+int32_t pcls_problem_info(const pcls_problem* p, pcls_info* info) {
+  if (!p || !info) return set_error(PCLS_E_INVALID, "NULL argument");
+  std::memset(info, 0, sizeof *info);
+  info->n_vars = p->n;
+  info->n_cons = p->m;
+  info->n_lits = p->L;
+  info->max_len = p->max_k;
+  info->n_classes = (int32_t)p->classes.size();
+  info->n_segments = (int32_t)p->segments.size();
+  info->tile_restarts = p->tile_restarts;
+  info->block_threads = p->block_threads;
+  info->workspace_bytes = p->image.size();
+  info->lds_bytes_per_restart = (size_t)p->n * 2 * sizeof(float);
+  clear_error();
+  return PCLS_OK;
+}
+
+int32_t pcls_upload(pcls_problem* p, void* d_ws, size_t bytes, void* stream) {
+  if (!p) return set_error(PCLS_E_INVALID, "problem handle is NULL");
+  if (!d_ws) return set_error(PCLS_E_WORKSPACE, "workspace pointer is NULL");
+  if (bytes < p->image.size())
+    return set_error(PCLS_E_WORKSPACE, "workspace of %zu bytes is smaller than the %zu bytes required", bytes,
+                     p->image.size());
+  if (((uintptr_t)d_ws & 255u) != 0) return set_error(PCLS_E_WORKSPACE, "workspace must be 256-byte aligned");
+  PCLS_HIP(hipMemcpyAsync(d_ws, p->image.data(), p->image.size(), hipMemcpyHostToDevice, (hipStream_t)stream),
+           "hipMemcpyAsync(workspace)");
+  uint8_t* b = (uint8_t*)d_ws;
+  ProblemDev& D = p->dev;
+  D.n = p->n;
+  D.m = p->m;
+  D.L = (int32_t)p->L;
+  D.n_segments = (int32_t)p->segments.size();
+  D.n_classes = (int32_t)p->classes.size();
+  D.f_const = p->f_const;
+  D.segments = (const Segment*)(b + p->off_segments);
+  D.classes = (const ClassRec*)(b + p->off_classes);
+  D.nodes = (const NodeRec*)(b + p->off_nodes);
+  D.sp = (const int8_t*)(b + p->off_sp);
+  D.litT = (const int32_t*)(b + p->off_litT);
+  D.c_k = (const int32_t*)(b + p->off_ck);
+  D.c_cls = (const int32_t*)(b + p->off_ccls);
+  D.c_w = (const float*)(b + p->off_cw);
+  D.row_ptr = (const int32_t*)(b + p->off_rowptr);
+  D.lit = (const int32_t*)(b + p->off_lit);
+  D.unit_weights = p->unit_weights;
+  D.max_k = p->max_k;
+  p->d_ws = d_ws;
+  p->ws_bytes = bytes;
+  clear_error();
+  return PCLS_OK;
+}
+
+int32_t pcls_init_restarts(const pcls_problem* p, int32_t R, uint64_t seed, float* d_x, void* stream) {
+  int32_t st = check_bound(p);
+  if (st != PCLS_OK) return st;
+  if (R < 0) return set_error(PCLS_E_INVALID, "R must be >= 0");
+  if (R == 0) return PCLS_OK;
+  if (!d_x) return set_error(PCLS_E_INVALID, "d_x is NULL");
+  const int R_pad = round_up64(R);
+  hipLaunchKernelGGL(init_kernel, dim3(R_pad / 64, p->n), dim3(64), 0, (hipStream_t)stream, d_x, p->n, R, R_pad,
+                     (uint32_t)seed, (uint32_t)(seed >> 32));
+  PCLS_HIP(hipGetLastError(), "init_kernel launch");
+  clear_error();
+  return PCLS_OK;
+}
+
+int32_t pcls_evaluate(const pcls_problem* p, int32_t R, const float* d_x, float* d_obj, float* d_grad,
+                      void* stream) {
+  int32_t st = check_bound(p);
+  if (st != PCLS_OK) return st;
+  if (R < 0) return set_error(PCLS_E_INVALID, "R must be >= 0");
+  if (R == 0) return PCLS_OK;
+  if (!d_x || !d_obj) return set_error(PCLS_E_INVALID, "d_x and d_obj must not be NULL");
+  st = launch_tile(p, R, const_cast<float*>(d_x), 0.f, 1, nullptr, d_obj, d_grad, (hipStream_t)stream);
+  if (st == PCLS_OK) clear_error();
+  return st;
+}
+
+int32_t pcls_step(const pcls_problem* p, int32_t R, float* d_x, float lr, int32_t n_steps, float* d_obj_trace,
+                  void* stream) {
+  int32_t st = check_bound(p);
+  if (st != PCLS_OK) return st;
+  if (R < 0 || n_steps < 0) return set_error(PCLS_E_INVALID, "R and n_steps must be >= 0");
+  if (!(lr == lr)) return set_error(PCLS_E_INVALID, "lr is NaN");
+  if (R == 0 || n_steps == 0) return PCLS_OK;
+  if (!d_x) return set_error(PCLS_E_INVALID, "d_x is NULL");
+  st = launch_tile(p, R, d_x, lr, n_steps, d_obj_trace, nullptr, nullptr, (hipStream_t)stream);
+  if (st == PCLS_OK) clear_error();
+  return st;
+}
+
+int32_t pcls_extract(const pcls_problem* p, int32_t R, const float* d_x, int8_t* d_assign, int32_t* d_unsat,
+                     int32_t* d_best, void* stream) {
+  int32_t st = check_bound(p);
+  if (st != PCLS_OK) return st;
+  if (R < 0) return set_error(PCLS_E_INVALID, "R must be >= 0");
+  if (R == 0) return PCLS_OK;
+  if (!d_x || !d_unsat) return set_error(PCLS_E_INVALID, "d_x and d_unsat must not be NULL");
+  hipStream_t s = (hipStream_t)stream;
+  const int R_pad = round_up64(R);
+  hipLaunchKernelGGL(fill_i32_kernel, dim3((R + 255) / 256), dim3(256), 0, s, d_unsat, 0, R);
+  PCLS_HIP(hipGetLastError(), "fill launch");
+  if (p->m > 0) {
+    const int chunk = 256;
+    hipLaunchKernelGGL(extract_count_kernel, dim3((R + 255) / 256, (p->m + chunk - 1) / chunk), dim3(256), 0, s,
+                       p->dev, d_x, R, R_pad, d_unsat, chunk);
+    PCLS_HIP(hipGetLastError(), "extract_count launch");
+  }
+  if (d_assign) {
+    hipLaunchKernelGGL(extract_assign_kernel, dim3((R + 63) / 64, (p->n + 63) / 64), dim3(256), 0, s, d_x, p->n, R,
+                       R_pad, d_assign);
+    PCLS_HIP(hipGetLastError(), "extract_assign launch");
+  }
+  if (d_best) {
+    hipLaunchKernelGGL(extract_best_kernel, dim3(1), dim3(1024), 0, s, d_unsat, R, d_best);
+    PCLS_HIP(hipGetLastError(), "extract_best launch");
+  }
+  clear_error();
+  return PCLS_OK;
+}
+
+int32_t pcls_set_launch(pcls_problem* p, int32_t tile_restarts, int32_t block_threads) {
+  if (!p) return set_error(PCLS_E_INVALID, "problem handle is NULL");
+  if (tile_restarts < 0 || tile_restarts > 64 || (tile_restarts & (tile_restarts - 1)))
+    return set_error(PCLS_E_INVALID, "tile_restarts %d must be 0 or a power of two <= 64", tile_restarts);
+  if (block_threads != 0 && block_threads != 256 && block_threads != 512 && block_threads != 1024)
+    return set_error(PCLS_E_INVALID, "block_threads %d must be 0, 256, 512 or 1024", block_threads);
+  if (tile_restarts > 0 && tile_restarts * p->max_group > kWave)
+    return set_error(PCLS_E_UNSUPPORTED, "tile_restarts %d too large for constraints of %d literals", tile_restarts,
+                     p->max_k);
+  if (tile_restarts > 0 && tile_lds_bytes(p->n, tile_restarts) > (size_t)160 * 1024)
+    return set_error(PCLS_E_UNSUPPORTED, "tile of %d restarts x %d variables exceeds LDS", tile_restarts, p->n);
+  p->tile_restarts = tile_restarts;
+  p->block_threads = block_threads;
+  clear_error();
+  return PCLS_OK;
+}
+
+int32_t pcls_destroy(pcls_problem* p) {
+  delete p;
+  return PCLS_OK;
+}
+
+const char* pcls_last_error(void) { return pcls::last_error(); }
+
+}  // extern "C"

@@ -1,0 +1,354 @@
+// Host planner: validation, constraint classes, evaluation kinds, inverse-DFT
+// weights, length-bucketed segments and the device image.
+#include "plan.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <new>
+#include <tuple>
+
+namespace pcls {
+
+static thread_local std::string g_error;
+
+int32_t set_error(int32_t code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_error = buf;
+  return code;
+}
+
+void clear_error() { g_error.clear(); }
+
+const char* last_error() { return g_error.c_str(); }
+
+// Whether a symmetric constraint holds with exactly t of its k literals true
+// (paper: Table 2 and Appendix A).
+static bool holds(int type, int k, int param, int t) {
+  switch (type) {
+    case PCLS_OR: return t >= 1;
+    case PCLS_XOR: return (t & 1) == param;
+    case PCLS_CARD_GE: return t >= param;
+    case PCLS_NAE: return t > 0 && t < k;
+    case PCLS_EO: return t == 1;
+    case PCLS_AMO: return t <= 1;
+    case PCLS_EK: return t == param;
+  }
+  return false;
+}
+
+struct ClassKey {
+  int type, k, param;
+  bool operator<(const ClassKey& o) const {
+    return std::tie(type, k, param) < std::tie(o.type, o.k, o.param);
+  }
+};
+
+// Evaluation kind from the shape of the spectrum.  FE = sum_t sp_t Pr[T = t]
+// where Pr[T = 0] = prod u_i, Pr[T = k] = prod p_i (u = (1+y)/2, p = (1-y)/2)
+// and sum_t (-1)^t Pr[T = t] = prod y_i.
+static void classify(const std::vector<int>& sp, bool force_generic, ClassRec& C) {
+  const int k = (int)sp.size() - 1;
+  bool all_eq = true, tail_eq = true, head_eq = true, alt = true, mid_eq = true;
+  for (int t = 0; t <= k; ++t) {
+    if (sp[t] != sp[0]) all_eq = false;
+    if (t >= 1 && sp[t] != sp[1]) tail_eq = false;
+    if (t <= k - 1 && sp[t] != sp[0]) head_eq = false;
+    if (sp[t] != ((t & 1) ? -sp[0] : sp[0])) alt = false;
+    if (t >= 1 && t <= k - 1 && sp[t] != sp[1]) mid_eq = false;
+  }
+  C.a = C.b = C.c1 = C.c2 = C.c0 = 0.f;
+  if (all_eq) {
+    C.kind = KIND_CONST;
+    C.c0 = (float)sp[0];
+    return;
+  }
+  if (!force_generic) {
+    if (tail_eq) {  // FE = sp_1 + (sp_0 - sp_1) prod u
+      C.kind = KIND_PROD1;
+      C.a = 0.5f;
+      C.b = 0.5f;
+      C.c0 = (float)sp[1];
+      C.c1 = (float)(sp[0] - sp[1]);
+      return;
+    }
+    if (head_eq) {  // FE = sp_0 + (sp_k - sp_0) prod p
+      C.kind = KIND_PROD1;
+      C.a = 0.5f;
+      C.b = -0.5f;
+      C.c0 = (float)sp[0];
+      C.c1 = (float)(sp[k] - sp[0]);
+      return;
+    }
+    if (alt) {  // FE = sp_0 prod y
+      C.kind = KIND_PROD1;
+      C.a = 0.f;
+      C.b = 1.f;
+      C.c0 = 0.f;
+      C.c1 = (float)sp[0];
+      return;
+    }
+    if (k >= 3 && mid_eq) {  // FE = s + (sp_0 - s) prod u + (sp_k - s) prod p
+      C.kind = KIND_PROD2;
+      C.a = 0.5f;
+      C.b = 0.5f;
+      C.c0 = (float)sp[1];
+      C.c1 = (float)(sp[0] - sp[1]);
+      C.c2 = (float)(sp[k] - sp[1]);
+      return;
+    }
+  }
+  C.kind = KIND_DFT;
+}
+
+// Inverse-DFT weights over the K = k + 1 roots of unity.  With
+// Q_m = prod_i (alpha_m + beta_m y_i), alpha_m = (1 + w^m)/2, beta_m = (1 - w^m)/2,
+// w = exp(2 pi i / K), Q_m is the characteristic function of T at 2 pi m / K,
+// so Pr[T = t] = (1/K) sum_m Q_m w^-tm and FE = sum_m chat_m Q_m with
+// chat_m = (1/K) sum_t sp_t w^-tm.  The angles use exact integer reduction
+// (t m mod K) and FP64 arithmetic; results are rounded once to float32.
+static void dft_weights(const std::vector<int>& sp, ClassRec& C, std::vector<NodeRec>& nodes) {
+  const int k = (int)sp.size() - 1;
+  const int K = k + 1;
+  const double two_pi = 6.283185307179586476925286766559;
+  auto chat = [&](int m, double& re, double& im) {
+    re = im = 0.0;
+    for (int t = 0; t <= k; ++t) {
+      long r = ((long)t * m) % K;
+      double ang = two_pi * (double)r / (double)K;
+      re += sp[t] * std::cos(ang);
+      im -= sp[t] * std::sin(ang);
+    }
+    re /= K;
+    im /= K;
+  };
+  double c0r, c0i;
+  chat(0, c0r, c0i);
+  C.c0 = (float)c0r;
+  C.nyquist = (K % 2 == 0) ? 1 : 0;
+  C.n_nodes = (K - 1) / 2;  // complex nodes 1..(K-1)/2; K even adds the real node K/2
+  C.node_off = (int32_t)nodes.size();
+  for (int m = 1; m <= C.n_nodes; ++m) {
+    double wr, wi;
+    chat(m, wr, wi);
+    double ang = two_pi * (double)m / (double)K;
+    double er = std::cos(ang), ei = std::sin(ang);
+    double ar = 0.5 * (1.0 + er), ai = 0.5 * ei;
+    double br = 0.5 * (1.0 - er), bi = -0.5 * ei;
+    NodeRec nd;
+    nd.ar = (float)ar;
+    nd.ai = (float)ai;
+    nd.br = (float)br;
+    nd.bi = (float)bi;
+    nd.wr = (float)(2.0 * wr);
+    nd.wi = (float)(2.0 * wi);
+    nd.gr = (float)(2.0 * (wr * br - wi * bi));
+    nd.gi = (float)(2.0 * (wr * bi + wi * br));
+    nodes.push_back(nd);
+  }
+  if (C.nyquist) {
+    double s = 0.0;
+    for (int t = 0; t <= k; ++t) s += (t & 1) ? -sp[t] : sp[t];
+    C.c1 = (float)(s / K);
+  }
+}
+
+static size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+int32_t build_plan(int32_t n, int32_t m, const int32_t* row_ptr, const int32_t* lit, const int8_t* type,
+                   const int32_t* param, const float* weight, const pcls_plan_options* options,
+                   pcls_problem** out, size_t* workspace_bytes) {
+  if (!out || !workspace_bytes) return set_error(PCLS_E_INVALID, "out and workspace_bytes must not be NULL");
+  *out = nullptr;
+  *workspace_bytes = 0;
+  if (n < 1) return set_error(PCLS_E_INVALID, "n_vars must be >= 1 (got %d)", n);
+  if (n > (1 << 29)) return set_error(PCLS_E_UNSUPPORTED, "n_vars %d exceeds 2^29", n);
+  if (m < 0) return set_error(PCLS_E_INVALID, "n_cons must be >= 0 (got %d)", m);
+  if (!row_ptr) return set_error(PCLS_E_INVALID, "row_ptr must not be NULL");
+  if (m > 0 && !type) return set_error(PCLS_E_INVALID, "type must not be NULL");
+  if (row_ptr[0] != 0) return set_error(PCLS_E_INVALID, "row_ptr[0] must be 0 (got %d)", row_ptr[0]);
+  for (int c = 0; c < m; ++c) {
+    int k = row_ptr[c + 1] - row_ptr[c];
+    if (k < 1) return set_error(PCLS_E_INVALID, "constraint %d has length %d (row_ptr must increase)", c, k);
+    if (k > kMaxK) return set_error(PCLS_E_UNSUPPORTED, "constraint %d has %d literals (max %d)", c, k, kMaxK);
+  }
+  const int64_t L = row_ptr[m];
+  if (L > 0 && !lit) return set_error(PCLS_E_INVALID, "lit must not be NULL");
+  const bool force_generic = options && options->force_generic;
+
+  std::vector<int32_t> stamp((size_t)n, -1);
+  for (int c = 0; c < m; ++c) {
+    int ty = type[c];
+    int k = row_ptr[c + 1] - row_ptr[c];
+    int pr = param ? param[c] : 0;
+    if (ty < PCLS_OR || ty > PCLS_EK) return set_error(PCLS_E_INVALID, "constraint %d: unknown type %d", c, ty);
+    if (ty == PCLS_XOR && (pr < 0 || pr > 1))
+      return set_error(PCLS_E_INVALID, "constraint %d: XOR parity must be 0 or 1 (got %d)", c, pr);
+    if ((ty == PCLS_CARD_GE || ty == PCLS_EK) && (pr < 0 || pr > k))
+      return set_error(PCLS_E_INVALID, "constraint %d: kappa %d outside [0, %d]", c, pr, k);
+    if (weight && !std::isfinite(weight[c]))
+      return set_error(PCLS_E_INVALID, "constraint %d: weight is not finite", c);
+    for (int i = row_ptr[c]; i < row_ptr[c + 1]; ++i) {
+      int l = lit[i];
+      if (l == 0 || l == INT32_MIN || (l > 0 ? l : -l) > n)
+        return set_error(PCLS_E_INVALID, "constraint %d: literal %d out of range [1, %d]", c, l, n);
+      int v = l > 0 ? l : -l;
+      if (stamp[v - 1] == c)
+        return set_error(PCLS_E_DUPVAR, "constraint %d: variable %d occurs twice", c, v);
+      stamp[v - 1] = c;
+    }
+  }
+
+  pcls_problem* P = new (std::nothrow) pcls_problem();
+  if (!P) return set_error(PCLS_E_INVALID, "out of host memory");
+  P->n = n;
+  P->m = m;
+  P->L = L;
+  P->force_generic = force_generic ? 1 : 0;
+
+  // ---- classes
+  std::map<ClassKey, int> class_of;
+  std::vector<int> cls_orig((size_t)m);
+  double f_const = 0.0;
+  for (int c = 0; c < m; ++c) {
+    int ty = type[c];
+    int k = row_ptr[c + 1] - row_ptr[c];
+    int pr = (ty == PCLS_XOR || ty == PCLS_CARD_GE || ty == PCLS_EK) ? (param ? param[c] : 0) : 0;
+    ClassKey key{ty, k, pr};
+    auto it = class_of.find(key);
+    if (it == class_of.end()) {
+      std::vector<int> sp((size_t)k + 1);
+      for (int t = 0; t <= k; ++t) sp[t] = holds(ty, k, pr, t) ? -1 : 1;
+      ClassRec C{};
+      C.k = k;
+      classify(sp, force_generic, C);
+      if (C.kind == KIND_DFT) dft_weights(sp, C, P->nodes);
+      C.sp_off = (int32_t)P->sp.size();
+      for (int t = 0; t <= k; ++t) P->sp.push_back((int8_t)sp[t]);
+      int id = (int)P->classes.size();
+      P->classes.push_back(C);
+      it = class_of.emplace(key, id).first;
+    }
+    cls_orig[c] = it->second;
+    const float w = weight ? weight[c] : 1.0f;
+    if (w != 1.0f) P->unit_weights = 0;
+    f_const += (double)w * (double)P->classes[it->second].c0;
+    P->max_k = std::max(P->max_k, k);
+  }
+  P->f_const = (float)f_const;
+
+  // ---- planned order: (kind, bucket, class, original index); CONST last
+  std::vector<int32_t> order((size_t)m);
+  for (int c = 0; c < m; ++c) order[c] = c;
+  auto seg_key = [&](int c) {
+    const ClassRec& C = P->classes[cls_orig[c]];
+    int kind = C.kind;
+    int b = kind == KIND_CONST ? 0 : bucket_of(C.k);
+    return std::make_tuple(kind, b, cls_orig[c], c);
+  };
+  std::sort(order.begin(), order.end(), [&](int a, int b) { return seg_key(a) < seg_key(b); });
+  P->perm = order;
+  P->c_k.resize(m);
+  P->c_cls.resize(m);
+  P->c_w.resize(m);
+  P->row_ptr.resize((size_t)m + 1);
+  P->lit.resize((size_t)L);
+  P->row_ptr[0] = 0;
+  for (int j = 0; j < m; ++j) {
+    int c = order[j];
+    int k = row_ptr[c + 1] - row_ptr[c];
+    P->c_k[j] = k;
+    P->c_cls[j] = cls_orig[c];
+    P->c_w[j] = weight ? weight[c] : 1.0f;
+    P->row_ptr[j + 1] = P->row_ptr[j] + k;
+    for (int i = 0; i < k; ++i) {
+      int l = lit[row_ptr[c] + i];
+      int v = (l > 0 ? l : -l) - 1;
+      P->lit[P->row_ptr[j] + i] = (v << 1) | (l < 0 ? 1 : 0);
+    }
+  }
+
+  // ---- segments and their transposed literal blocks
+  int j = 0;
+  while (j < m) {
+    const ClassRec& C0 = P->classes[P->c_cls[j]];
+    if (C0.kind == KIND_CONST) break;
+    int b = bucket_of(C0.k);
+    int e = j;
+    Segment S{};
+    S.kind = C0.kind;
+    S.bucket = b;
+    S.c_begin = j;
+    S.k_fixed = C0.k;
+    S.cls_fixed = P->c_cls[j];
+    S.m_max = 0;
+    while (e < m) {
+      const ClassRec& C = P->classes[P->c_cls[e]];
+      if (C.kind != S.kind || bucket_of(C.k) != b) break;
+      if (C.k != S.k_fixed) S.k_fixed = 0;
+      if (P->c_cls[e] != S.cls_fixed) S.cls_fixed = -1;
+      if (C.kind == KIND_DFT) S.m_max = std::max(S.m_max, C.n_nodes);
+      ++e;
+    }
+    S.c_count = e - j;
+    const int kmax = kBucketKmax[b];
+    S.lit_base = (int32_t)P->litT.size();
+    P->litT.resize(P->litT.size() + (size_t)kmax * S.c_count, 0);
+    for (int q = 0; q < S.c_count; ++q) {
+      int cj = j + q;
+      for (int i = 0; i < P->c_k[cj]; ++i)
+        P->litT[(size_t)S.lit_base + (size_t)i * S.c_count + q] = P->lit[P->row_ptr[cj] + i];
+    }
+    const int G = group_size(S.kind, kmax);
+    P->max_group = std::max(P->max_group, G);
+    P->segments.push_back(S);
+    j = e;
+  }
+
+  // ---- device image layout
+  size_t off = 0;
+  auto place = [&](size_t bytes) {
+    off = align_up(off, 256);
+    size_t at = off;
+    off += bytes;
+    return at;
+  };
+  P->off_segments = place(sizeof(Segment) * P->segments.size());
+  P->off_classes = place(sizeof(ClassRec) * P->classes.size());
+  P->off_nodes = place(sizeof(NodeRec) * P->nodes.size());
+  P->off_sp = place(P->sp.size());
+  P->off_litT = place(sizeof(int32_t) * P->litT.size());
+  P->off_ck = place(sizeof(int32_t) * (size_t)m);
+  P->off_ccls = place(sizeof(int32_t) * (size_t)m);
+  P->off_cw = place(sizeof(float) * (size_t)m);
+  P->off_rowptr = place(sizeof(int32_t) * ((size_t)m + 1));
+  P->off_lit = place(sizeof(int32_t) * (size_t)L);
+  size_t total = align_up(std::max<size_t>(off, 256), 256);
+  P->image.assign(total, 0);
+  auto put = [&](size_t at, const void* src, size_t bytes) {
+    if (bytes) std::memcpy(P->image.data() + at, src, bytes);
+  };
+  put(P->off_segments, P->segments.data(), sizeof(Segment) * P->segments.size());
+  put(P->off_classes, P->classes.data(), sizeof(ClassRec) * P->classes.size());
+  put(P->off_nodes, P->nodes.data(), sizeof(NodeRec) * P->nodes.size());
+  put(P->off_sp, P->sp.data(), P->sp.size());
+  put(P->off_litT, P->litT.data(), sizeof(int32_t) * P->litT.size());
+  put(P->off_ck, P->c_k.data(), sizeof(int32_t) * (size_t)m);
+  put(P->off_ccls, P->c_cls.data(), sizeof(int32_t) * (size_t)m);
+  put(P->off_cw, P->c_w.data(), sizeof(float) * (size_t)m);
+  put(P->off_rowptr, P->row_ptr.data(), sizeof(int32_t) * ((size_t)m + 1));
+  put(P->off_lit, P->lit.data(), sizeof(int32_t) * (size_t)L);
+
+  *out = P;
+  *workspace_bytes = total;
+  clear_error();
+  return PCLS_OK;
+}
+
+}  // namespace pcls

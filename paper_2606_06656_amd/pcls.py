@@ -1,0 +1,241 @@
+"""Python binding of libpcls (ctypes).
+
+Argument marshalling only: every step of the evaluation runs in the library's
+gfx950 kernels.  PyTorch provides device memory and the current HIP stream.
+
+State layout: X is a float32 device tensor of shape (n, R_pad), restart index
+contiguous, R_pad = round_up(R, 64).  `X[:, :R].T` is the (R, n) user view.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libpcls.so")
+
+PCLS_OK, PCLS_E_INVALID, PCLS_E_UNSUPPORTED, PCLS_E_DUPVAR, PCLS_E_WORKSPACE, PCLS_E_HIP = range(6)
+STATUS_NAMES = {0: "PCLS_OK", 1: "PCLS_E_INVALID", 2: "PCLS_E_UNSUPPORTED", 3: "PCLS_E_DUPVAR",
+                4: "PCLS_E_WORKSPACE", 5: "PCLS_E_HIP"}
+
+# exported entry points (checked by the CPU test suite against include/pcls.h)
+EXPORTS = ["pcls_plan", "pcls_plan_ex", "pcls_problem_info", "pcls_upload", "pcls_init_restarts",
+           "pcls_evaluate", "pcls_step", "pcls_extract", "pcls_set_launch", "pcls_destroy",
+           "pcls_last_error"]
+
+
+class PclsError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {message}")
+        self.status = status
+
+
+class PlanOptions(ctypes.Structure):
+    _fields_ = [("force_generic", ctypes.c_int32), ("reserved", ctypes.c_int32 * 7)]
+
+
+class Info(ctypes.Structure):
+    _fields_ = [("n_vars", ctypes.c_int32), ("n_cons", ctypes.c_int32), ("n_lits", ctypes.c_int64),
+                ("max_len", ctypes.c_int32), ("n_classes", ctypes.c_int32), ("n_segments", ctypes.c_int32),
+                ("tile_restarts", ctypes.c_int32), ("block_threads", ctypes.c_int32),
+                ("workspace_bytes", ctypes.c_size_t), ("lds_bytes_per_restart", ctypes.c_size_t)]
+
+
+_lib = None
+
+
+def load_library():
+    """Load libpcls.so; raises if it has not been built (there is no fallback)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_2606_06656_amd.build`")
+    L = ctypes.CDLL(LIB_PATH)
+    i32, u64, vp, sz = ctypes.c_int32, ctypes.c_uint64, ctypes.c_void_p, ctypes.c_size_t
+    P = ctypes.c_void_p
+    L.pcls_plan.restype = i32
+    L.pcls_plan.argtypes = [i32, i32, vp, vp, vp, vp, vp, ctypes.POINTER(P), ctypes.POINTER(sz)]
+    L.pcls_plan_ex.restype = i32
+    L.pcls_plan_ex.argtypes = [i32, i32, vp, vp, vp, vp, vp, ctypes.POINTER(PlanOptions), ctypes.POINTER(P),
+                               ctypes.POINTER(sz)]
+    L.pcls_problem_info.restype = i32
+    L.pcls_problem_info.argtypes = [P, ctypes.POINTER(Info)]
+    L.pcls_upload.restype = i32
+    L.pcls_upload.argtypes = [P, vp, sz, vp]
+    L.pcls_init_restarts.restype = i32
+    L.pcls_init_restarts.argtypes = [P, i32, u64, vp, vp]
+    L.pcls_evaluate.restype = i32
+    L.pcls_evaluate.argtypes = [P, i32, vp, vp, vp, vp]
+    L.pcls_step.restype = i32
+    L.pcls_step.argtypes = [P, i32, vp, ctypes.c_float, i32, vp, vp]
+    L.pcls_extract.restype = i32
+    L.pcls_extract.argtypes = [P, i32, vp, vp, vp, vp, vp]
+    L.pcls_set_launch.restype = i32
+    L.pcls_set_launch.argtypes = [P, i32, i32]
+    L.pcls_destroy.restype = i32
+    L.pcls_destroy.argtypes = [P]
+    L.pcls_last_error.restype = ctypes.c_char_p
+    L.pcls_last_error.argtypes = []
+    _lib = L
+    return L
+
+
+def check(status: int):
+    if status != PCLS_OK:
+        msg = load_library().pcls_last_error()
+        raise PclsError(status, msg.decode() if msg else "")
+
+
+def round_up64(R: int) -> int:
+    return (int(R) + 63) // 64 * 64
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data
+
+
+def _tptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream=None):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+class Plan:
+    """Host-side plan of a formula (no device memory)."""
+
+    def __init__(self, n, row_ptr, lit, ctype, param=None, weight=None, force_generic=False):
+        L = load_library()
+        self.n = int(n)
+        self._row_ptr = np.ascontiguousarray(row_ptr, np.int32)
+        self._lit = np.ascontiguousarray(lit, np.int32)
+        self._type = np.ascontiguousarray(ctype, np.int8)
+        self._param = None if param is None else np.ascontiguousarray(param, np.int32)
+        self._weight = None if weight is None else np.ascontiguousarray(weight, np.float32)
+        self.m = len(self._row_ptr) - 1
+        h = ctypes.c_void_p()
+        ws = ctypes.c_size_t()
+        opts = PlanOptions()
+        opts.force_generic = 1 if force_generic else 0
+        st = L.pcls_plan_ex(self.n, self.m, _ptr(self._row_ptr), _ptr(self._lit), _ptr(self._type),
+                            _ptr(self._param), _ptr(self._weight), ctypes.byref(opts), ctypes.byref(h),
+                            ctypes.byref(ws))
+        check(st)
+        self.handle = h
+        self.workspace_bytes = ws.value
+
+    @classmethod
+    def from_instance(cls, inst, force_generic=False):
+        return cls(inst.n, inst.row_ptr, inst.lit, inst.ctype, inst.param, inst.weight, force_generic)
+
+    def info(self) -> Info:
+        info = Info()
+        check(load_library().pcls_problem_info(self.handle, ctypes.byref(info)))
+        return info
+
+    def set_launch(self, tile_restarts=0, block_threads=0):
+        check(load_library().pcls_set_launch(self.handle, int(tile_restarts), int(block_threads)))
+
+    def close(self):
+        if getattr(self, "handle", None):
+            load_library().pcls_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Problem(Plan):
+    """A plan bound to a device workspace (a torch uint8 tensor)."""
+
+    def __init__(self, n, row_ptr, lit, ctype, param=None, weight=None, force_generic=False, device="cuda"):
+        import torch
+        super().__init__(n, row_ptr, lit, ctype, param, weight, force_generic)
+        dev = torch.device(device)
+        if dev.type == "cuda" and dev.index is None:
+            dev = torch.device("cuda", torch.cuda.current_device())
+        self.device = dev
+        self.workspace = torch.empty(max(self.workspace_bytes, 256) + 256, dtype=torch.uint8, device=self.device)
+        base = self.workspace.data_ptr()
+        self._ws_off = (-base) % 256
+        check(load_library().pcls_upload(self.handle, ctypes.c_void_p(base + self._ws_off), self.workspace_bytes,
+                                          _stream()))
+
+    @classmethod
+    def from_instance(cls, inst, force_generic=False, device="cuda"):
+        return cls(inst.n, inst.row_ptr, inst.lit, inst.ctype, inst.param, inst.weight, force_generic, device)
+
+    # ---- state
+    def new_state(self, R: int):
+        import torch
+        return torch.zeros((self.n, round_up64(R)), dtype=torch.float32, device=self.device)
+
+    def state_from_rows(self, x_rows):
+        """(R, n) array or tensor -> (n, R_pad) device state."""
+        import torch
+        x = torch.as_tensor(np.asarray(x_rows, np.float32) if not isinstance(x_rows, torch.Tensor) else x_rows,
+                            dtype=torch.float32)
+        R = x.shape[0]
+        X = self.new_state(R)
+        X[:, :R] = x.to(self.device).T
+        return X
+
+    def _check_state(self, X, R):
+        import torch
+        if not isinstance(X, torch.Tensor) or X.dtype != torch.float32 or not X.is_contiguous():
+            raise PclsError(PCLS_E_INVALID, "state must be a contiguous float32 tensor")
+        if tuple(X.shape) != (self.n, round_up64(R)):
+            raise PclsError(PCLS_E_INVALID, f"state shape {tuple(X.shape)} != {(self.n, round_up64(R))}")
+        if X.device != self.device:
+            raise PclsError(PCLS_E_INVALID, "state on another device")
+
+    # ---- operations
+    def init_restarts(self, X, R: int, seed: int):
+        self._check_state(X, R)
+        check(load_library().pcls_init_restarts(self.handle, int(R), int(seed) & (2 ** 64 - 1), _tptr(X),
+                                                _stream()))
+        return X
+
+    def evaluate(self, X, R: int, want_grad: bool = True):
+        import torch
+        self._check_state(X, R)
+        obj = torch.empty(R, dtype=torch.float32, device=self.device)
+        grad = torch.empty_like(X) if want_grad else None
+        check(load_library().pcls_evaluate(self.handle, int(R), _tptr(X), _tptr(obj), _tptr(grad), _stream()))
+        return obj, grad
+
+    def step(self, X, R: int, lr: float, n_steps: int = 1, trace: bool = False):
+        import torch
+        self._check_state(X, R)
+        tr = torch.empty((n_steps, R), dtype=torch.float32, device=self.device) if trace else None
+        check(load_library().pcls_step(self.handle, int(R), _tptr(X), float(lr), int(n_steps), _tptr(tr),
+                                       _stream()))
+        return tr
+
+    def extract(self, X, R: int, want_assign: bool = True):
+        import torch
+        self._check_state(X, R)
+        assign = torch.empty((R, self.n), dtype=torch.int8, device=self.device) if want_assign else None
+        unsat = torch.empty(R, dtype=torch.int32, device=self.device)
+        best = torch.empty(1, dtype=torch.int32, device=self.device)
+        check(load_library().pcls_extract(self.handle, int(R), _tptr(X), _tptr(assign), _tptr(unsat), _tptr(best),
+                                          _stream()))
+        return assign, unsat, best
+
+
+def solve(problem: Problem, R: int, steps: int, lr: float = 0.1, seed: int = 0):
+    """Random restarts + projected gradient descent + extraction."""
+    X = problem.new_state(R)
+    problem.init_restarts(X, R, seed)
+    problem.step(X, R, lr, steps)
+    assign, unsat, best = problem.extract(X, R)
+    return X, assign, unsat, best

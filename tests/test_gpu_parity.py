@@ -1,0 +1,289 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 oracle.
+
+Agreement asked (1e-5 relative): per constraint |dFE| <= 1e-5 and
+|d dFE/dy_i| <= 1e-5, both quantities lying in [-1, 1]; for whole problems the
+mixed bound |dF| <= 1e-5 max(|F|, s_F), |dg_v| <= 1e-5 max(|g_v|, s_v) with
+range scales s_F = sum_c |w_c| and s_v = sum of |w_c| over the occurrences of v.
+Clause-only problems (all constraints on the one-node product path) are held
+to the value-relative scales sum_c |w_c FE_c| and sum |w_c dFE_c/dy_i|.  The
+oracle always evaluates at the GPU's own float32 point (promoted exactly).
+"""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+from oracle import coeffs as C  # noqa: E402
+from oracle import native as N  # noqa: E402
+from paper_2606_06656_amd import pcls, synth  # noqa: E402
+from gpu_util import TOL, assert_obj_grad, corner_mix, log, oracle_for, range_scales, rows_of  # noqa: E402
+
+DEV = "cuda"
+
+K_LIST = [1, 2, 3, 4, 5, 6, 7, 8, 9, 12, 15, 16, 17, 24, 31, 32, 33, 48, 63, 64, 65, 96, 127, 128, 129, 192,
+          255, 256]
+
+
+def type_cases(k):
+    out = [(C.OR, 0), (C.XOR, 0), (C.XOR, 1), (C.NAE, 0), (C.EO, 0), (C.AMO, 0)]
+    for kap in sorted({0, 1, 2, (k + 1) // 2, k - 1, k}):
+        if 0 <= kap <= k:
+            out.append((C.CARD_GE, kap))
+    for kap in sorted({1, (k + 1) // 2}):
+        if kap <= k:
+            out.append((C.EK, kap))
+    return out
+
+
+def single_constraint(ctype, k, prm, rng):
+    lits = (np.arange(1, k + 1) * np.where(rng.random(k) < 0.5, -1, 1)).astype(np.int32)
+    rng.shuffle(lits)
+    return synth.Instance(n=k, row_ptr=np.array([0, k], np.int32), lit=lits, ctype=np.array([ctype], np.int8),
+                          param=np.array([prm], np.int32))
+
+
+@pytest.mark.parametrize("generic", [False, True])
+@pytest.mark.parametrize("k", K_LIST)
+def test_single_constraint_value_and_gradient(k, generic):
+    """FE and every dFE/dy_i of one constraint at 130 points (ragged R)."""
+    rng = np.random.default_rng(1000 + k + (7 if generic else 0))
+    R = 130
+    for ctype, prm in type_cases(k):
+        inst = single_constraint(ctype, k, prm, rng)
+        log(f"case k={k} type={C.TYPE_NAMES[ctype]} param={prm} generic={generic}")
+        prob = pcls.Problem.from_instance(inst, force_generic=generic)
+        x = corner_mix(rng, R, k)
+        X = prob.state_from_rows(x)
+        obj, grad = prob.evaluate(X, R)
+        torch.cuda.synchronize()
+        ref = oracle_for(inst).evaluate(x.astype(np.float64), method=N.PMF if k > 40 else N.AUTO)
+        fe_err = np.abs(obj.cpu().numpy() - ref["obj"])
+        assert fe_err.max() <= TOL, (ctype, prm, k, fe_err.max())
+        g = grad[:, :R].T.cpu().numpy()
+        g_err = np.abs(g - ref["grad"])
+        assert g_err.max() <= TOL, (ctype, prm, k, g_err.max())
+        # padding columns carry no NaN from the kernels
+        assert torch.isfinite(grad[:, R:]).all()
+
+
+@pytest.mark.parametrize("generic", [False, True])
+@pytest.mark.parametrize("seed", [0, 1])
+def test_mixed_problem_all_types(seed, generic):
+    inst = synth.mixed_small(n=96, seed=seed, kmax=64, count=300)
+    log(f"case mixed_small seed={seed} generic={generic} m={inst.m} L={inst.L}")
+    prob = pcls.Problem.from_instance(inst, force_generic=generic)
+    rng = np.random.default_rng(seed)
+    R = 100
+    x = corner_mix(rng, R, inst.n)
+    X = prob.state_from_rows(x)
+    obj, grad = prob.evaluate(X, R)
+    ref = oracle_for(inst).evaluate(rows_of(X, R), method=N.PMF)
+    assert_obj_grad(obj.cpu().numpy(), grad[:, :R].T.cpu().numpy(), ref, what="mixed", inst=inst)
+
+
+def test_weighted_constraints():
+    inst = synth.mixed_small(n=64, seed=11, kmax=20, count=150)
+    inst.weight = np.random.default_rng(11).uniform(0.25, 3.0, inst.m).astype(np.float32)
+    log("case weighted")
+    prob = pcls.Problem.from_instance(inst)
+    R = 70
+    x = corner_mix(np.random.default_rng(12), R, inst.n)
+    X = prob.state_from_rows(x)
+    obj, grad = prob.evaluate(X, R)
+    ref = oracle_for(inst).evaluate(rows_of(X, R), method=N.PMF)
+    assert_obj_grad(obj.cpu().numpy(), grad[:, :R].T.cpu().numpy(), ref, what="weighted", inst=inst)
+
+
+@pytest.mark.parametrize("seed", range(10))
+def test_c1_every_step(seed):
+    """3-SAT n=50, m=213, R=64, 200 steps of lr 0.1: objective and gradient at
+    every iterate, and each step against clip(x - lr g_oracle)."""
+    inst = synth.c1_3sat(seed)
+    log(f"case c1 seed={seed}")
+    prob = pcls.Problem.from_instance(inst)
+    op = oracle_for(inst)
+    R, lr = 64, 0.1
+    X = prob.new_state(R)
+    prob.init_restarts(X, R, seed)
+    for t in range(200):
+        xt = rows_of(X, R)
+        obj, grad = prob.evaluate(X, R)
+        ref = op.evaluate(xt, method=N.ESP)
+        assert_obj_grad(obj.cpu().numpy(), grad[:, :R].T.cpu().numpy(), ref, what=f"c1 step {t}")
+        prob.step(X, R, lr, 1)
+        x1 = rows_of(X, R)
+        expect = np.clip(xt - lr * ref["grad"], -1, 1)
+        slack = lr * TOL * np.maximum(np.abs(ref["grad"]), ref["sig_grad"]) + 2.0 ** -22
+        assert np.all(np.abs(x1 - expect) <= slack), f"step {t}"
+
+
+def test_trace_semantics():
+    inst = synth.c1_3sat(3)
+    log("case trace")
+    prob = pcls.Problem.from_instance(inst)
+    R, lr, S = 64, 0.1, 6
+    X = prob.new_state(R)
+    prob.init_restarts(X, R, 3)
+    X2 = X.clone()
+    tr = prob.step(X, R, lr, S, trace=True).cpu().numpy()
+    for s in range(S):
+        obj, _ = prob.evaluate(X2, R, want_grad=False)
+        ref = oracle_for(inst).evaluate(rows_of(X2, R), method=N.ESP)
+        np.testing.assert_allclose(tr[s], obj.cpu().numpy(), atol=1e-4)
+        assert_obj_grad(tr[s], None, ref, what=f"trace {s}")
+        prob.step(X2, R, lr, 1)
+    np.testing.assert_allclose(X.cpu().numpy(), X2.cpu().numpy(), atol=1e-5)
+
+
+def test_c2_sampled_steps():
+    """Mixed n=2000 instance, 1024 restarts, 1000 steps; 16 restarts checked at
+    steps 0, 1, 10, 100 and 999 (objective, gradient and the next step)."""
+    inst = synth.c2_mixed()
+    log("case c2")
+    prob = pcls.Problem.from_instance(inst)
+    op = oracle_for(inst)
+    R, lr = 1024, 0.1
+    X = prob.new_state(R)
+    prob.init_restarts(X, R, 2)
+    sample = np.random.default_rng(2).choice(R, 16, replace=False)
+    done = 0
+    for t in (0, 1, 10, 100, 999):
+        if t > done:
+            prob.step(X, R, lr, t - done)
+            done = t
+        xt = rows_of(X, R)[sample]
+        obj, grad = prob.evaluate(X, R)
+        ref = op.evaluate(xt, method=N.ESP)
+        g = grad[:, :R].T.cpu().numpy()[sample]
+        assert_obj_grad(obj.cpu().numpy()[sample], g, ref, what=f"c2 step {t}", inst=inst)
+        Xn = X.clone()
+        prob.step(Xn, R, lr, 1)
+        x1 = rows_of(Xn, R)[sample]
+        expect = np.clip(xt - lr * ref["grad"], -1, 1)
+        slack = lr * TOL * np.maximum(np.abs(ref["grad"]), range_scales(inst)[1]) + 2.0 ** -22
+        assert np.all(np.abs(x1 - expect) <= slack), f"c2 step {t}"
+
+
+def test_c3_full_size_sampled():
+    """Long-support n=20000, m=40000, R=4096 evaluated at full size; 3 sampled restarts."""
+    inst = synth.c3_long()
+    log(f"case c3 L={inst.L}")
+    prob = pcls.Problem.from_instance(inst)
+    R = 4096
+    X = prob.new_state(R)
+    prob.init_restarts(X, R, 3)
+    prob.step(X, R, 0.1, 2)
+    obj, grad = prob.evaluate(X, R)
+    sample = np.array([0, 1777, 4095])
+    xt = rows_of(X, R)[sample]
+    ref = oracle_for(inst, with_coefficients=False).evaluate(xt, method=N.PMF)
+    g = grad[:, :R].T.cpu().numpy()[sample]
+    assert_obj_grad(obj.cpu().numpy()[sample], g, ref, what="c3", inst=inst)
+
+
+def test_c3_forced_long():
+    inst = synth.c3_forced_long()
+    log(f"case c3 forced long L={inst.L}")
+    prob = pcls.Problem.from_instance(inst)
+    R = 64
+    rng = np.random.default_rng(31)
+    x = corner_mix(rng, R, inst.n)
+    X = prob.state_from_rows(x)
+    obj, grad = prob.evaluate(X, R)
+    sample = np.array([0, 5, 17, 20, 40, 63])
+    ref = oracle_for(inst, with_coefficients=False).evaluate(rows_of(X, R)[sample], method=N.PMF)
+    assert_obj_grad(obj.cpu().numpy()[sample], grad[:, :R].T.cpu().numpy()[sample], ref, what="c3 long", inst=inst)
+
+
+@pytest.mark.parametrize("T,block", [(1, 256), (2, 512), (4, 1024), (8, 512), (16, 1024)])
+def test_launch_settings_agree(T, block):
+    inst = synth.c2_mixed(seed=5, n=600, n_or=1800, n_xor=180, n_card=60)
+    log(f"case launch T={T} block={block}")
+    prob = pcls.Problem.from_instance(inst)
+    prob.set_launch(T, block)
+    R = 200
+    x = corner_mix(np.random.default_rng(5), R, inst.n)
+    X = prob.state_from_rows(x)
+    obj, grad = prob.evaluate(X, R)
+    ref = oracle_for(inst).evaluate(rows_of(X, R), method=N.ESP)
+    assert_obj_grad(obj.cpu().numpy(), grad[:, :R].T.cpu().numpy(), ref, what=f"T={T}", inst=inst)
+
+
+def test_init_restarts_bit_exact():
+    inst = synth.c1_3sat(0)
+    prob = pcls.Problem.from_instance(inst)
+    for R, seed in [(100, 7), (64, 2 ** 40 + 5), (1, 0)]:
+        log(f"case init R={R} seed={seed}")
+        X = prob.new_state(R)
+        X.fill_(7.0)
+        prob.init_restarts(X, R, seed)
+        ref = N.init_uniform(R, inst.n, seed)
+        assert np.array_equal(rows_of(X, R), ref)
+        assert torch.all(X[:, R:] == 0)
+
+
+@pytest.mark.parametrize("seed", [0, 4])
+def test_extract_exact(seed):
+    inst = synth.mixed_small(n=80, seed=seed, kmax=30, count=200)
+    log(f"case extract seed={seed}")
+    prob = pcls.Problem.from_instance(inst)
+    R = 150
+    x = corner_mix(np.random.default_rng(seed), R, inst.n)
+    x[3, :5] = [0.0, -0.0, 1e-30, -1e-30, -1.0]
+    X = prob.state_from_rows(x)
+    assign, unsat, best = prob.extract(X, R)
+    a_ref, u_ref, b_ref = oracle_for(inst).extract(rows_of(X, R))
+    assert np.array_equal(assign.cpu().numpy(), a_ref)
+    assert np.array_equal(unsat.cpu().numpy(), u_ref)
+    assert int(best.item()) == b_ref
+
+
+def test_planted_solution_found_by_extract():
+    counts = {C.OR: 40, C.XOR: 20, C.CARD_GE: 20, C.NAE: 20, C.EO: 10, C.AMO: 10, C.EK: 10}
+    inst, z = synth.planted(120, counts, seed=8)
+    log("case planted")
+    prob = pcls.Problem.from_instance(inst)
+    R = 3
+    x = np.stack([z * 0.5, -z * 0.5, z]).astype(np.float32)
+    X = prob.state_from_rows(x)
+    _, unsat, best = prob.extract(X, R)
+    u = unsat.cpu().numpy()
+    assert u[0] == 0 and u[2] == 0 and int(best.item()) == 0
+    obj, _ = prob.evaluate(X, R)
+    assert abs(obj.cpu().numpy()[2] + inst.m) <= 1e-5 * inst.m
+
+
+def test_empty_and_degenerate():
+    # no constraints: F = 0, gradient 0, nothing violated
+    inst = synth.Instance(n=10, row_ptr=np.zeros(1, np.int32), lit=np.zeros(0, np.int32),
+                          ctype=np.zeros(0, np.int8), param=np.zeros(0, np.int32))
+    log("case empty")
+    prob = pcls.Problem.from_instance(inst)
+    R = 5
+    X = prob.state_from_rows(np.full((R, 10), 0.3, np.float32))
+    obj, grad = prob.evaluate(X, R)
+    assert torch.all(obj == 0) and torch.all(grad == 0)
+    _, unsat, _ = prob.extract(X, R)
+    assert torch.all(unsat == 0)
+    prob.step(X, R, 0.1, 0)
+    # constant constraints only (CARD >= 0 always holds, NAE of one literal never holds)
+    inst = synth.Instance(n=3, row_ptr=np.array([0, 2, 3], np.int32), lit=np.array([1, -2, 3], np.int32),
+                          ctype=np.array([C.CARD_GE, C.NAE], np.int8), param=np.array([0, 0], np.int32))
+    prob = pcls.Problem.from_instance(inst)
+    X = prob.state_from_rows(np.array([[0.2, -0.4, 0.9]], np.float32))
+    obj, grad = prob.evaluate(X, 1)
+    assert obj.item() == 0.0 and torch.all(grad == 0)
+    _, unsat, _ = prob.extract(X, 1)
+    assert unsat.item() == 1
+
+
+def test_state_too_large_for_lds_is_reported():
+    n = 20481
+    inst = synth.random_ksat(n, 10, 3, seed=1)
+    prob = pcls.Problem.from_instance(inst)
+    X = prob.new_state(1)
+    with pytest.raises(pcls.PclsError) as e:
+        prob.evaluate(X, 1)
+    assert e.value.status == pcls.PCLS_E_UNSUPPORTED
