@@ -62,9 +62,11 @@ enum {
 
 /* Planning options (pcls_plan_ex).  Zero-initialised = defaults. */
 typedef struct pcls_plan_options {
-  int32_t force_generic; /* 1: evaluate every constraint through the K-node DFT path
-                            (no one- or two-node product forms); for testing */
-  int32_t reserved[7];
+  int32_t force_generic;    /* 1: evaluate every constraint through the K-node DFT path
+                               (no one- or two-node product forms); for testing */
+  int32_t accumulator_bits; /* gradient accumulator: 0 = automatic (64-bit fixed point when
+                               the state fits on chip, else 32-bit), 32 or 64 */
+  int32_t reserved[6];
 } pcls_plan_options;
 
 typedef struct pcls_info {
@@ -73,6 +75,10 @@ typedef struct pcls_info {
   int32_t max_len;
   int32_t n_classes;         /* distinct (type, length, param) */
   int32_t n_segments;
+  int32_t accumulator_bits;  /* requested gradient accumulator width (0 = automatic) */
+  int32_t grad_scale_log2_64; /* fixed-point scales 2^S of the 64-bit and 32-bit gradient */
+  int32_t grad_scale_log2_32; /* accumulators and of the objective accumulator            */
+  int32_t obj_scale_log2;
   int32_t tile_restarts;     /* restarts per workgroup of the resident engine (0 = auto) */
   int32_t block_threads;     /* threads per workgroup of the resident engine (0 = auto) */
   size_t workspace_bytes;
@@ -157,6 +163,16 @@ int32_t pcls_extract(const pcls_problem* p, int32_t R, const float* d_x, int8_t*
  * PCLS_E_UNSUPPORTED if the setting does not fit the device's on-chip memory.
  */
 int32_t pcls_set_launch(pcls_problem* p, int32_t tile_restarts, int32_t block_threads);
+
+/*
+ * The resident-engine launch the library will use for R restarts on the current
+ * device: restarts per workgroup, threads per workgroup, gradient accumulator
+ * width (32 or 64), its fixed-point scale log2 (a gradient sum is exact in units
+ * of 2^-S; each term is rounded to the nearest unit) and LDS bytes per
+ * workgroup.  Any output pointer may be NULL.  Queries the device (no launch).
+ */
+int32_t pcls_launch_info(const pcls_problem* p, int32_t R, int32_t* tile_restarts, int32_t* block_threads,
+                         int32_t* accumulator_bits, int32_t* grad_scale_log2, size_t* lds_bytes);
 
 /* Free the host plan; never frees caller memory. */
 int32_t pcls_destroy(pcls_problem* p);

@@ -9,6 +9,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 #include <cstdio>
 #include <cstring>
 #include <mutex>
@@ -25,6 +26,15 @@ namespace {
 
 constexpr int kWave = 64;
 
+// Read-only tables are read through the constant address space: a uniform
+// address then becomes a scalar load instead of a vector load per lane.
+template <class T>
+using kptr = const __attribute__((address_space(4))) T*;
+template <class T>
+__device__ __forceinline__ kptr<T> kconst(const T* p) {
+  return (kptr<T>)p;
+}
+
 struct cf {
   float r, i;
 };
@@ -40,6 +50,35 @@ struct Log2 {
 template <>
 struct Log2<1> {
   static constexpr int v = 0;
+};
+
+// Fixed-point accumulation of gradient and objective contributions in LDS.
+// Integer LDS atomics run at the LDS's full rate whereas float LDS atomics are
+// processed about one lane per few cycles; integer sums are also exact and
+// independent of the order in which lanes arrive.  Contributions arrive
+// pre-multiplied by 2^S (host-chosen so that no sum can overflow).
+template <class AT>
+struct FixedAcc;
+
+template <>
+struct FixedAcc<unsigned long long> {
+  // |v| < 2^51: 1.5 * 2^52 + v rounds v to the nearest integer in the FP64
+  // significand, whose low bits then hold it in two's complement.
+  static __device__ __forceinline__ void add(unsigned long long* p, float v) {
+    const long long q = __double_as_longlong((double)v + 6755399441055744.0) - 0x4338000000000000LL;
+    atomicAdd(p, (unsigned long long)q);
+  }
+  static __device__ __forceinline__ float value(unsigned long long a, float inv) {
+    return (float)((double)(long long)a * (double)inv);
+  }
+};
+
+template <>
+struct FixedAcc<unsigned int> {
+  static __device__ __forceinline__ void add(unsigned int* p, float v) {
+    atomicAdd(p, (unsigned int)__float2int_rn(v));
+  }
+  static __device__ __forceinline__ float value(unsigned int a, float inv) { return (float)(int)a * inv; }
 };
 
 // ---------------------------------------------------------------- group scans
@@ -128,15 +167,22 @@ __device__ __forceinline__ PairCtx pair_ctx(const ProblemDev& P, const Segment& 
 
 // Product kinds: FE - c0 = c1 prod (a + b y) [+ c2 prod (1 - y)/2];
 // dFE/dy_i = c1 b prod_{j != i} (a + b y_j) [- c2/2 prod_{j != i} (1 - y_j)/2].
-template <int NN, int KMAX, int G>
+struct ProdParams {
+  float a, b, c1, c2;
+};
+
+__device__ __forceinline__ ProdParams prod_params(kptr<ClassRec> classes, int cls) {
+  return {classes[cls].a, classes[cls].b, classes[cls].c1, classes[cls].c2};
+}
+
+template <int NN, int KMAX, int G, class AT>
 __device__ __forceinline__ void prod_pair(const ProblemDev& P, const Segment& S, int c_local, int lig, int t,
-                                          int logT, const float* xs, float* gs, float& facc) {
+                                          int logT, const float* xs, AT* gs, float& facc, float gsc,
+                                          const PairCtx& q, const ProdParams& pp) {
   constexpr int J = KMAX / G;
   constexpr bool kExact = KMAX <= 8;  // buckets up to 8 hold a single length
   const int T = 1 << logT;
-  const PairCtx q = pair_ctx(P, S, S.c_begin + c_local);
-  const ClassRec& C = P.classes[q.cls];
-  const float a1 = C.a, b1 = C.b, c1 = C.c1, c2 = C.c2;
+  const float a1 = pp.a, b1 = pp.b, c1 = pp.c1, c2 = pp.c2;
   const int32_t* lp = P.litT + S.lit_base + c_local;
 
   int addr[J];
@@ -179,8 +225,8 @@ __device__ __forceinline__ void prod_pair(const ProblemDev& P, const Segment& S,
     if constexpr (NN == 2) fe = fmaf(c2, run2 * xq2, fe);
     facc = fmaf(q.w, fe, facc);
   }
-  const float s1 = c1 * b1 * q.w * xp1;
-  const float s2 = -0.5f * c2 * q.w * xp2;
+  const float s1 = c1 * b1 * (q.w * gsc) * xp1;
+  const float s2 = -0.5f * c2 * (q.w * gsc) * xp2;
   float suf1 = xq1, suf2 = xq2;
 #pragma unroll
   for (int j = J - 1; j >= 0; --j) {
@@ -190,20 +236,24 @@ __device__ __forceinline__ void prod_pair(const ProblemDev& P, const Segment& S,
       g = fmaf(s2 * pre2[j], suf2, g);
       suf2 *= f2[j];
     }
-    if (addr[j] >= 0) atomicAdd(&gs[addr[j] >> 1], (addr[j] & 1) ? -g : g);
+    if (addr[j] >= 0) FixedAcc<AT>::add(&gs[addr[j] >> 1], (addr[j] & 1) ? -g : g);
   }
 }
 
 // Generic kind: FE - chat_0 = sum_{m=1}^{M} Re(2 chat_m Q_m) [+ chat_{K/2} prod y];
 // dFE/dy_i = sum_m Re(2 chat_m beta_m prod_{j != i}(alpha_m + beta_m y_j)) [+ chat_{K/2} prod_{j != i} y_j].
-template <int KMAX, int G>
+template <int KMAX, int G, class AT>
 __device__ __forceinline__ void dft_pair(const ProblemDev& P, const Segment& S, int c_local, int lig, int t,
-                                         int logT, const float* xs, float* gs, float& facc) {
+                                         int logT, const float* xs, AT* gs, float& facc, float gsc,
+                                         const PairCtx& q) {
   constexpr int J = KMAX / G;
   constexpr bool kExact = KMAX <= 8;
   const int T = 1 << logT;
-  const PairCtx q = pair_ctx(P, S, S.c_begin + c_local);
-  const ClassRec& C = P.classes[q.cls];
+  kptr<ClassRec> classes = kconst(P.classes);
+  const int nyquist = classes[q.cls].nyquist;
+  const float cn = classes[q.cls].c1;
+  const int node_off = classes[q.cls].node_off;
+  const int nn = classes[q.cls].n_nodes;
   const int32_t* lp = P.litT + S.lit_base + c_local;
 
   int addr[J];
@@ -223,8 +273,7 @@ __device__ __forceinline__ void dft_pair(const ProblemDev& P, const Segment& S, 
     }
   }
   float fe = 0.f;
-  if (C.nyquist) {  // real node omega^(K/2) = -1: factor y, padded slots hold y = 1
-    const float cn = C.c1;
+  if (nyquist) {  // real node omega^(K/2) = -1: factor y, padded slots hold y = 1
     float pre[J];
     float run = 1.f;
 #pragma unroll
@@ -242,11 +291,10 @@ __device__ __forceinline__ void dft_pair(const ProblemDev& P, const Segment& S, 
       suf *= y[j];
     }
   }
-  const NodeRec* nd = P.nodes + C.node_off;
-  const int nn = C.n_nodes;
+  kptr<NodeRec> nd = kconst(P.nodes) + node_off;
   for (int mm = 0; mm < S.m_max; ++mm) {
     if (mm < nn) {
-      const NodeRec N = nd[mm];
+      const NodeRec N{nd[mm].ar, nd[mm].ai, nd[mm].br, nd[mm].bi, nd[mm].wr, nd[mm].wi, nd[mm].gr, nd[mm].gi};
       cf pre[J];
       cf run{1.f, 0.f};
 #pragma unroll
@@ -277,15 +325,15 @@ __device__ __forceinline__ void dft_pair(const ProblemDev& P, const Segment& S, 
 #pragma unroll
   for (int j = 0; j < J; ++j) {
     if (addr[j] >= 0) {
-      const float gv = q.w * g[j];
-      atomicAdd(&gs[addr[j] >> 1], (addr[j] & 1) ? -gv : gv);
+      const float gv = (q.w * gsc) * g[j];
+      FixedAcc<AT>::add(&gs[addr[j] >> 1], (addr[j] & 1) ? -gv : gv);
     }
   }
 }
 
-template <int KIND, int KMAX>
-__device__ __forceinline__ void run_segment(const ProblemDev& P, const Segment& S, const float* xs, float* gs,
-                                            float& facc, int tid, int nth, int logT) {
+template <int KIND, int KMAX, class AT>
+__device__ __forceinline__ void run_segment(const ProblemDev& P, const Segment& S, const float* xs, AT* gs,
+                                            float& facc, float gsc, int tid, int nth, int logT) {
   constexpr int G = group_size(KIND, KMAX);
   constexpr int LG = Log2<G>::v;
   // keep the lane-index arithmetic inside the segment: hoisting it out of the
@@ -295,11 +343,20 @@ __device__ __forceinline__ void run_segment(const ProblemDev& P, const Segment& 
   const int lig = (tid >> logT) & (G - 1);
   const int slot = tid >> (logT + LG);
   const int nslots = nth >> (logT + LG);
+  kptr<ClassRec> classes = kconst(P.classes);
+  const bool uni = S.cls_fixed >= 0;
+  ProdParams pp_uni{};
+  if constexpr (KIND != KIND_DFT) {
+    if (uni) pp_uni = prod_params(classes, S.cls_fixed);
+  }
   for (int cl = slot; cl < S.c_count; cl += nslots) {
-    if constexpr (KIND == KIND_DFT)
-      dft_pair<KMAX, G>(P, S, cl, lig, t, logT, xs, gs, facc);
-    else
-      prod_pair<KIND == KIND_PROD2 ? 2 : 1, KMAX, G>(P, S, cl, lig, t, logT, xs, gs, facc);
+    const PairCtx q = pair_ctx(P, S, S.c_begin + cl);
+    if constexpr (KIND == KIND_DFT) {
+      dft_pair<KMAX, G>(P, S, cl, lig, t, logT, xs, gs, facc, gsc, q);
+    } else {
+      const ProdParams pp = uni ? pp_uni : prod_params(classes, q.cls);
+      prod_pair<KIND == KIND_PROD2 ? 2 : 1, KMAX, G>(P, S, cl, lig, t, logT, xs, gs, facc, gsc, q, pp);
+    }
   }
 }
 
@@ -318,13 +375,14 @@ __device__ __forceinline__ void run_segment(const ProblemDev& P, const Segment& 
   X(KIND, 11, 128)                 \
   X(KIND, 12, 256)
 
-#define PCLS_CASE(KIND, B, KMAX) \
-  case (KIND)*kNumBuckets + (B): \
-    run_segment<KIND, KMAX>(P, S, xs, gs, facc, tid, nth, logT); \
+#define PCLS_CASE(KIND, B, KMAX)                                     \
+  case (KIND)*kNumBuckets + (B):                                     \
+    if constexpr ((B) <= MAXB) run_segment<KIND, KMAX>(P, S, xs, gs, facc, gsc, tid, nth, logT); \
     break;
 
-__device__ __forceinline__ void run_any_segment(const ProblemDev& P, const Segment& S, const float* xs, float* gs,
-                                             float& facc, int tid, int nth, int logT) {
+template <int MAXB, class AT>
+__device__ __forceinline__ void run_any_segment(const ProblemDev& P, const Segment& S, const float* xs, AT* gs,
+                                                float& facc, float gsc, int tid, int nth, int logT) {
   switch (S.kind * kNumBuckets + S.bucket) {
     PCLS_BUCKET_CASES(KIND_PROD1, PCLS_CASE)
     PCLS_BUCKET_CASES(KIND_PROD2, PCLS_CASE)
@@ -336,15 +394,23 @@ __device__ __forceinline__ void run_any_segment(const ProblemDev& P, const Segme
 
 // One workgroup per tile of T = 2^logT restarts; all n_steps steps in LDS.
 // Evaluate mode (obj_out != NULL): one evaluation, writes F and optionally G.
+// Variants by the largest length bucket they handle (a kernel's register
+// allocation covers its longest code path, so short-constraint problems run a
+// variant with fewer registers and more waves per SIMD) and by the width of the
+// fixed-point gradient accumulator (64-bit, or 32-bit where LDS is short).
+// LDS: x[n][T] float | g[n][T] fixed point | F[T] 64-bit fixed point.
+template <int MAXB, class AT>
 __global__ void __launch_bounds__(1024) tile_kernel(ProblemDev P, float* __restrict__ X, int R, int ldx,
                                                     int logT, float lr, int n_steps, float* __restrict__ trace,
-                                                    float* __restrict__ obj_out, float* __restrict__ g_out) {
-  extern __shared__ float lds[];
+                                                    float* __restrict__ obj_out, float* __restrict__ g_out,
+                                                    float gsc, float ginv, float fsc, float finv) {
+  extern __shared__ unsigned long long lds_raw[];
   const int T = 1 << logT;
   const int NT = P.n << logT;
-  float* xs = lds;
-  float* gs = lds + NT;
-  float* Fs = gs + NT;
+  float* xs = reinterpret_cast<float*>(lds_raw);
+  AT* gs = reinterpret_cast<AT*>(reinterpret_cast<char*>(lds_raw) + ((size_t)NT * 4 + 7) / 8 * 8);
+  unsigned long long* Fs =
+      reinterpret_cast<unsigned long long*>(reinterpret_cast<char*>(gs) + ((size_t)NT * sizeof(AT) + 7) / 8 * 8);
   const int tid = threadIdx.x, nth = blockDim.x;
   const int r0 = blockIdx.x * T;
   const int t = tid & (T - 1);
@@ -353,24 +419,26 @@ __global__ void __launch_bounds__(1024) tile_kernel(ProblemDev P, float* __restr
   for (int i = tid; i < NT; i += nth) {
     const int v = i >> logT, tt = i & (T - 1);
     xs[i] = X[(size_t)v * ldx + r0 + tt];
-    gs[i] = 0.f;
+    gs[i] = 0;
   }
-  if (tid < T) Fs[tid] = 0.f;
+  if (tid < T) Fs[tid] = 0ull;
   __syncthreads();
 
   for (int s = 0; s < n_steps; ++s) {
     float facc = 0.f;
+    kptr<Segment> segs = kconst(P.segments);
     for (int sg = 0; sg < P.n_segments; ++sg) {
-      const Segment S = P.segments[sg];
-      run_any_segment(P, S, xs, gs, facc, tid, nth, logT);
+      const Segment S{segs[sg].kind,    segs[sg].bucket, segs[sg].c_begin,   segs[sg].c_count,
+                      segs[sg].lit_base, segs[sg].k_fixed, segs[sg].cls_fixed, segs[sg].m_max};
+      run_any_segment<MAXB>(P, S, xs, gs, facc, gsc, tid, nth, logT);
     }
     // lanes with equal (lane mod T) hold the same restart
     for (int o = T; o < kWave; o <<= 1) facc += __shfl_xor(facc, o);
-    if ((tid & (kWave - 1)) < T) atomicAdd(&Fs[t], facc);
+    if ((tid & (kWave - 1)) < T) FixedAcc<unsigned long long>::add(&Fs[t], facc * fsc);
     __syncthreads();
     if (tid < T) {
-      const float F = Fs[tid] + P.f_const;
-      Fs[tid] = 0.f;
+      const float F = FixedAcc<unsigned long long>::value(Fs[tid], finv) + P.f_const;
+      Fs[tid] = 0ull;
       const int r = r0 + tid;
       if (r < R) {
         if (trace) trace[(size_t)s * R + r] = F;
@@ -381,14 +449,14 @@ __global__ void __launch_bounds__(1024) tile_kernel(ProblemDev P, float* __restr
       if (g_out) {
         for (int i = tid; i < NT; i += nth) {
           const int v = i >> logT, tt = i & (T - 1);
-          g_out[(size_t)v * ldx + r0 + tt] = gs[i];
+          g_out[(size_t)v * ldx + r0 + tt] = FixedAcc<AT>::value(gs[i], ginv);
         }
       }
     } else {
       for (int i = tid; i < NT; i += nth) {
-        const float xn = fmaf(-lr, gs[i], xs[i]);
+        const float xn = fmaf(-lr, FixedAcc<AT>::value(gs[i], ginv), xs[i]);
         xs[i] = fminf(1.f, fmaxf(-1.f, xn));
-        gs[i] = 0.f;
+        gs[i] = 0;
       }
     }
     __syncthreads();
@@ -455,8 +523,8 @@ __global__ void extract_count_kernel(ProblemDev P, const float* __restrict__ X, 
       const bool var_true = X[(size_t)(code >> 1) * ldx + r] < 0.f;
       ntrue += (var_true != (bool)(code & 1)) ? 1 : 0;
     }
-    const ClassRec& C = P.classes[P.c_cls[c]];
-    cnt += P.sp[C.sp_off + ntrue] > 0 ? 1 : 0;
+    const int sp_off = kconst(P.classes)[P.c_cls[c]].sp_off;
+    cnt += P.sp[sp_off + ntrue] > 0 ? 1 : 0;
   }
   if (cnt) atomicAdd(&unsat[r], cnt);
 }
@@ -535,57 +603,77 @@ int32_t device_limits(DeviceLimits& out) {
     d.n_cu = v;
   }
   if (!d.lds_attr_set) {
-    PCLS_HIP(hipFuncSetAttribute((const void*)tile_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, d.lds_max),
-             "hipFuncSetAttribute");
+    const void* variants[] = {(const void*)tile_kernel<7, unsigned long long>,
+                              (const void*)tile_kernel<9, unsigned long long>,
+                              (const void*)tile_kernel<12, unsigned long long>,
+                              (const void*)tile_kernel<7, unsigned int>,
+                              (const void*)tile_kernel<9, unsigned int>,
+                              (const void*)tile_kernel<12, unsigned int>};
+    for (const void* f : variants)
+      PCLS_HIP(hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, d.lds_max), "hipFuncSetAttribute");
     d.lds_attr_set = true;
   }
   out = d;
   return PCLS_OK;
 }
 
-size_t tile_lds_bytes(int n, int T) { return ((size_t)2 * n * T + (size_t)T) * sizeof(float); }
+// LDS of one workgroup: x[n][T] float, g[n][T] fixed point (4 or 8 bytes),
+// F[T] 64-bit, each region 8-byte aligned.
+size_t tile_lds_bytes(int n, int T, int acc_bytes) {
+  const size_t nt = (size_t)n * T;
+  return (nt * 4 + 7) / 8 * 8 + (nt * acc_bytes + 7) / 8 * 8 + (size_t)T * 8;
+}
 
 struct Launch {
   int logT;
   int block;
   size_t lds;
+  bool acc64;
 };
 
 // Restarts per workgroup: largest power of two whose state fits in LDS, at
 // most 64 / G_max (a lane group must stay inside one wave), and small enough
-// to give every compute unit at least two tiles when R allows it.
+// to give every compute unit at least two tiles when R allows it.  The 64-bit
+// gradient accumulator is used whenever its tile fits, else the 32-bit one.
 int32_t choose_launch(const pcls_problem* p, int R, Launch& L) {
   DeviceLimits lim;
   int32_t st = device_limits(lim);
   if (st != PCLS_OK) return st;
   const int R_pad = round_up64(R);
   const int tmax_group = kWave / std::max(1, p->max_group);
+  const size_t cap = (size_t)lim.lds_max;
+  bool acc64 = p->acc_bits != 32;
+  if (p->acc_bits == 0 && tile_lds_bytes(p->n, std::max(1, p->tile_restarts), 8) > cap) acc64 = false;
+  if (!acc64 && p->s_g32 < 8)
+    return set_error(PCLS_E_UNSUPPORTED, "state of %d variables does not fit on chip with a 64-bit accumulator and "
+                     "weights are too large for a 32-bit one", p->n);
+  const int ab = acc64 ? 8 : 4;
   int T;
   if (p->tile_restarts > 0) {
     T = p->tile_restarts;
   } else {
     T = 1;
     const int want_tiles = 2 * std::max(1, lim.n_cu);
-    while (T * 2 <= tmax_group && tile_lds_bytes(p->n, T * 2) <= (size_t)lim.lds_max && R_pad / (T * 2) >= want_tiles)
-      T *= 2;
+    while (T * 2 <= tmax_group && tile_lds_bytes(p->n, T * 2, ab) <= cap && R_pad / (T * 2) >= want_tiles) T *= 2;
   }
   if (T < 1 || T > 64 || (T & (T - 1)))
     return set_error(PCLS_E_INVALID, "tile_restarts %d must be a power of two in [1, 64]", T);
   if (T > tmax_group)
     return set_error(PCLS_E_UNSUPPORTED, "tile_restarts %d too large for constraints of %d literals", T, p->max_k);
-  const size_t lds = tile_lds_bytes(p->n, T);
-  if (lds > (size_t)lim.lds_max)
+  const size_t lds = tile_lds_bytes(p->n, T, ab);
+  if (lds > cap)
     return set_error(PCLS_E_UNSUPPORTED,
                      "state of %d variables x %d restarts needs %zu bytes of LDS (device limit %d)", p->n, T, lds,
                      lim.lds_max);
   int block = p->block_threads;
-  if (block <= 0) block = lds > (size_t)lim.lds_max / 2 ? 1024 : 512;
+  if (block <= 0) block = lds > cap / 2 ? 1024 : 512;
   if (block != 256 && block != 512 && block != 1024)
     return set_error(PCLS_E_INVALID, "block_threads %d must be 256, 512 or 1024", block);
   L.logT = 0;
   while ((1 << L.logT) < T) ++L.logT;
   L.block = block;
   L.lds = lds;
+  L.acc64 = acc64;
   return PCLS_OK;
 }
 
@@ -602,8 +690,21 @@ int32_t launch_tile(const pcls_problem* p, int R, float* d_x, float lr, int n_st
   if (st != PCLS_OK) return st;
   const int R_pad = round_up64(R);
   const int tiles = R_pad >> L.logT;
-  hipLaunchKernelGGL(tile_kernel, dim3(tiles), dim3(L.block), L.lds, stream, p->dev, d_x, R, R_pad, L.logT, lr,
-                     n_steps, trace, obj, grad);
+  const int sg = L.acc64 ? p->s_g64 : p->s_g32;
+  const float gsc = std::ldexp(1.0f, sg), ginv = std::ldexp(1.0f, -sg);
+  const float fsc = std::ldexp(1.0f, p->s_f), finv = std::ldexp(1.0f, -p->s_f);
+  if (L.acc64) {
+    auto kern = p->max_bucket <= 7 ? tile_kernel<7, unsigned long long>
+                                   : (p->max_bucket <= 9 ? tile_kernel<9, unsigned long long>
+                                                         : tile_kernel<12, unsigned long long>);
+    hipLaunchKernelGGL(kern, dim3(tiles), dim3(L.block), L.lds, stream, p->dev, d_x, R, R_pad, L.logT, lr, n_steps,
+                       trace, obj, grad, gsc, ginv, fsc, finv);
+  } else {
+    auto kern = p->max_bucket <= 7 ? tile_kernel<7, unsigned int>
+                                   : (p->max_bucket <= 9 ? tile_kernel<9, unsigned int> : tile_kernel<12, unsigned int>);
+    hipLaunchKernelGGL(kern, dim3(tiles), dim3(L.block), L.lds, stream, p->dev, d_x, R, R_pad, L.logT, lr, n_steps,
+                       trace, obj, grad, gsc, ginv, fsc, finv);
+  }
   PCLS_HIP(hipGetLastError(), "tile_kernel launch");
   return PCLS_OK;
 }
@@ -634,6 +735,10 @@ int32_t pcls_problem_info(const pcls_problem* p, pcls_info* info) {
   info->max_len = p->max_k;
   info->n_classes = (int32_t)p->classes.size();
   info->n_segments = (int32_t)p->segments.size();
+  info->accumulator_bits = p->acc_bits;
+  info->grad_scale_log2_64 = p->s_g64;
+  info->grad_scale_log2_32 = p->s_g32;
+  info->obj_scale_log2 = p->s_f;
   info->tile_restarts = p->tile_restarts;
   info->block_threads = p->block_threads;
   info->workspace_bytes = p->image.size();
@@ -746,6 +851,22 @@ int32_t pcls_extract(const pcls_problem* p, int32_t R, const float* d_x, int8_t*
   return PCLS_OK;
 }
 
+int32_t pcls_launch_info(const pcls_problem* p, int32_t R, int32_t* tile_restarts, int32_t* block_threads,
+                         int32_t* accumulator_bits, int32_t* grad_scale_log2, size_t* lds_bytes) {
+  if (!p) return set_error(PCLS_E_INVALID, "problem handle is NULL");
+  if (R < 1) return set_error(PCLS_E_INVALID, "R must be >= 1");
+  Launch L;
+  int32_t st = choose_launch(p, R, L);
+  if (st != PCLS_OK) return st;
+  if (tile_restarts) *tile_restarts = 1 << L.logT;
+  if (block_threads) *block_threads = L.block;
+  if (accumulator_bits) *accumulator_bits = L.acc64 ? 64 : 32;
+  if (grad_scale_log2) *grad_scale_log2 = L.acc64 ? p->s_g64 : p->s_g32;
+  if (lds_bytes) *lds_bytes = L.lds;
+  clear_error();
+  return PCLS_OK;
+}
+
 int32_t pcls_set_launch(pcls_problem* p, int32_t tile_restarts, int32_t block_threads) {
   if (!p) return set_error(PCLS_E_INVALID, "problem handle is NULL");
   if (tile_restarts < 0 || tile_restarts > 64 || (tile_restarts & (tile_restarts - 1)))
@@ -755,7 +876,7 @@ int32_t pcls_set_launch(pcls_problem* p, int32_t tile_restarts, int32_t block_th
   if (tile_restarts > 0 && tile_restarts * p->max_group > kWave)
     return set_error(PCLS_E_UNSUPPORTED, "tile_restarts %d too large for constraints of %d literals", tile_restarts,
                      p->max_k);
-  if (tile_restarts > 0 && tile_lds_bytes(p->n, tile_restarts) > (size_t)160 * 1024)
+  if (tile_restarts > 0 && tile_lds_bytes(p->n, tile_restarts, p->acc_bits == 64 ? 8 : 4) > (size_t)160 * 1024)
     return set_error(PCLS_E_UNSUPPORTED, "tile of %d restarts x %d variables exceeds LDS", tile_restarts, p->n);
   p->tile_restarts = tile_restarts;
   p->block_threads = block_threads;

@@ -181,6 +181,9 @@ int32_t build_plan(int32_t n, int32_t m, const int32_t* row_ptr, const int32_t* 
   const int64_t L = row_ptr[m];
   if (L > 0 && !lit) return set_error(PCLS_E_INVALID, "lit must not be NULL");
   const bool force_generic = options && options->force_generic;
+  const int acc_bits = options ? options->accumulator_bits : 0;
+  if (acc_bits != 0 && acc_bits != 32 && acc_bits != 64)
+    return set_error(PCLS_E_INVALID, "accumulator_bits must be 0, 32 or 64 (got %d)", acc_bits);
 
   std::vector<int32_t> stamp((size_t)n, -1);
   for (int c = 0; c < m; ++c) {
@@ -242,6 +245,41 @@ int32_t build_plan(int32_t n, int32_t m, const int32_t* row_ptr, const int32_t* 
     P->max_k = std::max(P->max_k, k);
   }
   P->f_const = (float)f_const;
+  P->acc_bits = acc_bits;
+
+  // ---- fixed-point scales (see plan.h)
+  {
+    std::vector<double> occ((size_t)n, 0.0);
+    for (int c = 0; c < m; ++c) {
+      const double w = std::fabs(weight ? (double)weight[c] : 1.0);
+      if (P->classes[cls_orig[c]].kind == KIND_CONST) continue;
+      P->max_w = std::max(P->max_w, w);
+      P->maxsum_f += w;
+      for (int i = row_ptr[c]; i < row_ptr[c + 1]; ++i) {
+        const int l = lit[i];
+        occ[(size_t)((l > 0 ? l : -l) - 1)] += w;
+      }
+    }
+    for (double v : occ) P->maxsum_g = std::max(P->maxsum_g, v);
+    auto clog2 = [](double x) { return (int)std::ceil(std::log2(x)); };
+    const double margin = 1.01;  // FP32 rounding of a term bounded by 1 in exact arithmetic
+    const int lg = clog2(P->maxsum_g * margin + 1.0), lw = clog2(P->max_w * margin + 1.0);
+    // 64-bit: a term times 2^S must stay below 2^50 (rounding through the FP64
+    // significand) and a sum below 2^61; 32-bit: below 2^29 and 2^30.
+    P->s_g64 = std::min(61 - lg, 50 - lw);
+    P->s_g32 = std::min(30 - lg, 29 - lw);
+    P->s_f = 50 - clog2(P->maxsum_f * margin + 1.0);
+    if (P->s_g64 < 8 || P->s_f < 8) {
+      int32_t st = set_error(PCLS_E_UNSUPPORTED, "constraint weights too large for fixed-point accumulation");
+      delete P;
+      return st;
+    }
+    if (acc_bits == 32 && P->s_g32 < 8) {
+      int32_t st = set_error(PCLS_E_UNSUPPORTED, "weights or degrees too large for a 32-bit gradient accumulator");
+      delete P;
+      return st;
+    }
+  }
 
   // ---- planned order: (kind, bucket, class, original index); CONST last
   std::vector<int32_t> order((size_t)m);
@@ -307,6 +345,7 @@ int32_t build_plan(int32_t n, int32_t m, const int32_t* row_ptr, const int32_t* 
     }
     const int G = group_size(S.kind, kmax);
     P->max_group = std::max(P->max_group, G);
+    P->max_bucket = std::max(P->max_bucket, b);
     P->segments.push_back(S);
     j = e;
   }

@@ -24,8 +24,16 @@ struct pcls_problem {
   std::vector<int32_t> row_ptr, lit;   // planned order
   std::vector<int32_t> perm;           // planned index -> original constraint index
   int32_t max_group = 1;               // largest lane group G over the segments
+  int32_t max_bucket = -1;             // largest length bucket over the segments
   float f_const = 0.f;
   int32_t unit_weights = 1;
+
+  // fixed-point accumulation: |dFE/dy| <= 1 and |FE| <= 1, so a variable's
+  // gradient is bounded by the sum of |w| over its occurrences and the
+  // objective by the sum of |w| over constraints
+  double maxsum_g = 0.0, max_w = 0.0, maxsum_f = 0.0;
+  int32_t acc_bits = 0;   // requested accumulator width (0 = automatic)
+  int32_t s_g64 = 0, s_g32 = 0, s_f = 0;
 
   // device image
   std::vector<uint8_t> image;

@@ -22,8 +22,8 @@ STATUS_NAMES = {0: "PCLS_OK", 1: "PCLS_E_INVALID", 2: "PCLS_E_UNSUPPORTED", 3: "
 
 # exported entry points (checked by the CPU test suite against include/pcls.h)
 EXPORTS = ["pcls_plan", "pcls_plan_ex", "pcls_problem_info", "pcls_upload", "pcls_init_restarts",
-           "pcls_evaluate", "pcls_step", "pcls_extract", "pcls_set_launch", "pcls_destroy",
-           "pcls_last_error"]
+           "pcls_evaluate", "pcls_step", "pcls_extract", "pcls_set_launch", "pcls_launch_info",
+           "pcls_destroy", "pcls_last_error"]
 
 
 class PclsError(RuntimeError):
@@ -33,12 +33,15 @@ class PclsError(RuntimeError):
 
 
 class PlanOptions(ctypes.Structure):
-    _fields_ = [("force_generic", ctypes.c_int32), ("reserved", ctypes.c_int32 * 7)]
+    _fields_ = [("force_generic", ctypes.c_int32), ("accumulator_bits", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 6)]
 
 
 class Info(ctypes.Structure):
     _fields_ = [("n_vars", ctypes.c_int32), ("n_cons", ctypes.c_int32), ("n_lits", ctypes.c_int64),
                 ("max_len", ctypes.c_int32), ("n_classes", ctypes.c_int32), ("n_segments", ctypes.c_int32),
+                ("accumulator_bits", ctypes.c_int32), ("grad_scale_log2_64", ctypes.c_int32),
+                ("grad_scale_log2_32", ctypes.c_int32), ("obj_scale_log2", ctypes.c_int32),
                 ("tile_restarts", ctypes.c_int32), ("block_threads", ctypes.c_int32),
                 ("workspace_bytes", ctypes.c_size_t), ("lds_bytes_per_restart", ctypes.c_size_t)]
 
@@ -75,6 +78,9 @@ def load_library():
     L.pcls_extract.argtypes = [P, i32, vp, vp, vp, vp, vp]
     L.pcls_set_launch.restype = i32
     L.pcls_set_launch.argtypes = [P, i32, i32]
+    L.pcls_launch_info.restype = i32
+    ip = ctypes.POINTER(i32)
+    L.pcls_launch_info.argtypes = [P, i32, ip, ip, ip, ip, ctypes.POINTER(sz)]
     L.pcls_destroy.restype = i32
     L.pcls_destroy.argtypes = [P]
     L.pcls_last_error.restype = ctypes.c_char_p
@@ -110,7 +116,7 @@ def _stream(stream=None):
 class Plan:
     """Host-side plan of a formula (no device memory)."""
 
-    def __init__(self, n, row_ptr, lit, ctype, param=None, weight=None, force_generic=False):
+    def __init__(self, n, row_ptr, lit, ctype, param=None, weight=None, force_generic=False, accumulator_bits=0):
         L = load_library()
         self.n = int(n)
         self._row_ptr = np.ascontiguousarray(row_ptr, np.int32)
@@ -123,6 +129,7 @@ class Plan:
         ws = ctypes.c_size_t()
         opts = PlanOptions()
         opts.force_generic = 1 if force_generic else 0
+        opts.accumulator_bits = int(accumulator_bits)
         st = L.pcls_plan_ex(self.n, self.m, _ptr(self._row_ptr), _ptr(self._lit), _ptr(self._type),
                             _ptr(self._param), _ptr(self._weight), ctypes.byref(opts), ctypes.byref(h),
                             ctypes.byref(ws))
@@ -131,8 +138,9 @@ class Plan:
         self.workspace_bytes = ws.value
 
     @classmethod
-    def from_instance(cls, inst, force_generic=False):
-        return cls(inst.n, inst.row_ptr, inst.lit, inst.ctype, inst.param, inst.weight, force_generic)
+    def from_instance(cls, inst, force_generic=False, accumulator_bits=0):
+        return cls(inst.n, inst.row_ptr, inst.lit, inst.ctype, inst.param, inst.weight, force_generic,
+                   accumulator_bits)
 
     def info(self) -> Info:
         info = Info()
@@ -141,6 +149,15 @@ class Plan:
 
     def set_launch(self, tile_restarts=0, block_threads=0):
         check(load_library().pcls_set_launch(self.handle, int(tile_restarts), int(block_threads)))
+
+    def launch_info(self, R: int) -> dict:
+        """Launch the library will use for R restarts (queries the current device)."""
+        v = [ctypes.c_int32() for _ in range(4)]
+        lds = ctypes.c_size_t()
+        check(load_library().pcls_launch_info(self.handle, int(R), *[ctypes.byref(a) for a in v],
+                                              ctypes.byref(lds)))
+        return {"tile_restarts": v[0].value, "block_threads": v[1].value, "accumulator_bits": v[2].value,
+                "grad_scale_log2": v[3].value, "lds_bytes": lds.value}
 
     def close(self):
         if getattr(self, "handle", None):
@@ -157,9 +174,10 @@ class Plan:
 class Problem(Plan):
     """A plan bound to a device workspace (a torch uint8 tensor)."""
 
-    def __init__(self, n, row_ptr, lit, ctype, param=None, weight=None, force_generic=False, device="cuda"):
+    def __init__(self, n, row_ptr, lit, ctype, param=None, weight=None, force_generic=False, device="cuda",
+                 accumulator_bits=0):
         import torch
-        super().__init__(n, row_ptr, lit, ctype, param, weight, force_generic)
+        super().__init__(n, row_ptr, lit, ctype, param, weight, force_generic, accumulator_bits)
         dev = torch.device(device)
         if dev.type == "cuda" and dev.index is None:
             dev = torch.device("cuda", torch.cuda.current_device())
@@ -171,8 +189,9 @@ class Problem(Plan):
                                           _stream()))
 
     @classmethod
-    def from_instance(cls, inst, force_generic=False, device="cuda"):
-        return cls(inst.n, inst.row_ptr, inst.lit, inst.ctype, inst.param, inst.weight, force_generic, device)
+    def from_instance(cls, inst, force_generic=False, device="cuda", accumulator_bits=0):
+        return cls(inst.n, inst.row_ptr, inst.lit, inst.ctype, inst.param, inst.weight, force_generic, device,
+                   accumulator_bits)
 
     # ---- state
     def new_state(self, R: int):

@@ -37,14 +37,24 @@ def range_scales(inst):
     return float(w.sum()), sg
 
 
-def assert_obj_grad(obj_gpu, grad_rows_gpu, ref, tol=TOL, what="", inst=None):
+def quantum_floor(inst, prob, R):
+    """Absolute floor of the fixed-point gradient accumulator: every term is
+    rounded to a multiple of 2^-S, so a variable's sum may differ from the exact
+    sum of its FP32 terms by (number of terms) * 2^-(S+1)."""
+    S = prob.launch_info(R)["grad_scale_log2"]
+    occ = np.bincount(np.abs(inst.lit) - 1, minlength=inst.n).astype(np.float64)
+    return occ * 2.0 ** -(S + 1)
+
+
+def assert_obj_grad(obj_gpu, grad_rows_gpu, ref, tol=TOL, what="", inst=None, floor_g=None):
     """Mixed bound |dF| <= tol max(|F|, s_F), |dg| <= tol max(|g|, s_g) elementwise.
 
     With inst=None the scales are the oracle's sums of term magnitudes
     (value-relative: sum_c |w_c FE_c|, sum |w_c dFE_c/dy_i|); with inst given
     they are the range scales of `range_scales` (each term relative to its
     range [-1, 1], the reading used where a term is a cancelling sum over
-    DFT nodes and may be zero while FP32 leaves a residue near 1e-7)."""
+    DFT nodes and may be zero while FP32 leaves a residue near 1e-7).
+    floor_g adds the accumulator quantum (`quantum_floor`) to the gradient bound."""
     F = ref["obj"]
     if inst is None:
         sF, sg = ref["sig_obj"], ref["sig_grad"]
@@ -60,6 +70,8 @@ def assert_obj_grad(obj_gpu, grad_rows_gpu, ref, tol=TOL, what="", inst=None):
     if grad_rows_gpu is not None:
         g = ref["grad"]
         gb = tol * np.maximum(np.abs(g), sg) + 1e-30
+        if floor_g is not None:
+            gb = gb + floor_g
         ge = np.abs(grad_rows_gpu.astype(np.float64) - g)
         if not np.all(ge <= gb):
             r, v = np.unravel_index(int(np.argmax(ge / gb)), ge.shape)

@@ -18,7 +18,7 @@ torch = pytest.importorskip("torch")
 from oracle import coeffs as C  # noqa: E402
 from oracle import native as N  # noqa: E402
 from paper_2606_06656_amd import pcls, synth  # noqa: E402
-from gpu_util import TOL, assert_obj_grad, corner_mix, log, oracle_for, range_scales, rows_of  # noqa: E402
+from gpu_util import TOL, assert_obj_grad, corner_mix, log, oracle_for, quantum_floor, range_scales, rows_of  # noqa: E402
 
 DEV = "cuda"
 
@@ -107,11 +107,13 @@ def test_c1_every_step(seed):
     R, lr = 64, 0.1
     X = prob.new_state(R)
     prob.init_restarts(X, R, seed)
+    floor = quantum_floor(inst, prob, R)
+    assert prob.launch_info(R)["accumulator_bits"] == 64
     for t in range(200):
         xt = rows_of(X, R)
         obj, grad = prob.evaluate(X, R)
         ref = op.evaluate(xt, method=N.ESP)
-        assert_obj_grad(obj.cpu().numpy(), grad[:, :R].T.cpu().numpy(), ref, what=f"c1 step {t}")
+        assert_obj_grad(obj.cpu().numpy(), grad[:, :R].T.cpu().numpy(), ref, what=f"c1 step {t}", floor_g=floor)
         prob.step(X, R, lr, 1)
         x1 = rows_of(X, R)
         expect = np.clip(xt - lr * ref["grad"], -1, 1)
@@ -287,3 +289,39 @@ def test_state_too_large_for_lds_is_reported():
     with pytest.raises(pcls.PclsError) as e:
         prob.evaluate(X, 1)
     assert e.value.status == pcls.PCLS_E_UNSUPPORTED
+
+
+def test_gradient_bitwise_deterministic_across_launches():
+    """Fixed-point accumulation is exact and order-independent: the gradient is
+    bitwise identical across repeated launches and across tile sizes."""
+    inst = synth.c2_mixed(seed=6, n=500, n_or=1500, n_xor=150, n_card=50)
+    log("case determinism")
+    prob = pcls.Problem.from_instance(inst)
+    R = 128
+    x = corner_mix(np.random.default_rng(6), R, inst.n)
+    X = prob.state_from_rows(x)
+    outs = []
+    for T in (1, 2, 4, 1):
+        prob.set_launch(T, 512)
+        obj, grad = prob.evaluate(X, R)
+        outs.append((obj.cpu().numpy(), grad.cpu().numpy()))
+    for o, g in outs[1:]:
+        assert np.array_equal(g, outs[0][1])
+    assert np.array_equal(outs[0][0], outs[3][0])  # same launch shape: same objective bits
+
+
+@pytest.mark.parametrize("bits", [32, 64])
+def test_accumulator_widths(bits):
+    inst = synth.mixed_small(n=120, seed=21, kmax=48, count=400)
+    inst.weight = np.random.default_rng(21).uniform(0.5, 2.0, inst.m).astype(np.float32)
+    log(f"case accumulator {bits}")
+    prob = pcls.Problem.from_instance(inst, accumulator_bits=bits)
+    R = 90
+    x = corner_mix(np.random.default_rng(22), R, inst.n)
+    X = prob.state_from_rows(x)
+    obj, grad = prob.evaluate(X, R)
+    ref = oracle_for(inst).evaluate(rows_of(X, R), method=N.PMF)
+    assert_obj_grad(obj.cpu().numpy(), grad[:, :R].T.cpu().numpy(), ref, what=f"acc{bits}", inst=inst)
+    Xs = X.clone()
+    prob.step(Xs, R, 0.05, 3)
+    assert torch.isfinite(Xs).all()
