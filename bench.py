@@ -41,6 +41,8 @@ def workload(name: str):
         return synth.c3_long(), 4096, 0.1, "long_support_n20000_m40000_geomk3to256_R4096"
     if name == "c3long":
         return synth.c3_forced_long(), 512, 0.1, "forced_long_n20000_k64to256_R512"
+    if name == "c4":
+        return synth.c4_batch(256), 64, 0.1, "batch256_nlogu100to10000_or3r4.2_xor5r0.1_R64each"
     if name == "c1":
         return synth.c1_3sat(0), 64, 0.1, "3sat_n50_m213_R64"
     raise SystemExit(f"unknown workload {name}")
@@ -99,12 +101,79 @@ def cpu_baseline(inst, lr: float, budget_s: float = 12.0, R_sample: int = 16):
                       f"{el:.1f} s"}
 
 
+def bench_batch(args, insts, R, lr, key):
+    """Many uneven instances: one persistent launch per captured graph replay
+    (configuration from the autotuner) against per-instance plain launches."""
+    import torch
+
+    from paper_2606_06656_amd import pcls
+    from paper_2606_06656_amd.batch import Batch
+
+    probs = [pcls.Problem.from_instance(i, device="cuda:0") for i in insts]
+    states = []
+    for k, p in enumerate(probs):
+        X = p.new_state(R)
+        p.init_restarts(X, R, 4000 + k)
+        states.append(X)
+    b = Batch(probs, [R] * len(probs), states)
+    tune = b.autotune(lr, probe_steps=3)
+    S = args.graph_steps
+    reps = max(1, args.steps // S)
+    steps = reps * S
+    b.capture(lr, S)
+    for _ in range(max(1, args.warmup // S)):
+        b.replay()
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        b.replay()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    L_tot = sum(i.L for i in insts)
+    n_tot = sum(i.n for i in insts)
+    m_tot = sum(i.m for i in insts)
+    value = R * L_tot * steps / (ms / 1e3)
+    # per-instance plain launches: one pcls_step(1) per instance per step
+    bs = args.baseline_steps
+    e0.record(stream)
+    for _ in range(bs):
+        for p, X in zip(probs, states):
+            p.step(X, R, lr, 1)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms_b = e0.elapsed_time(e1)
+    base_rate = R * L_tot * bs / (ms_b / 1e3)
+    alg = sum(algorithmic_bytes_per_step(i.n, i.m, i.L, R) for i in insts) * S
+    achieved = alg / (ms / reps / 1e3) / 1e9
+    cfg = b.config()
+    out = {
+        "metric": METRIC, "value": value, "unit": "literal-evals/s", "n_gpus": 1, "steps": steps,
+        "warmup": args.warmup, "ms_per_step": ms / steps, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": key, "instances": len(insts), "sum_n": n_tot, "sum_m": m_tot, "sum_L": L_tot,
+                   "restarts_each": R, "lr": lr, "graph_steps": S, "autotune": tune, "batch": cfg},
+        "per_instance_launches": {"value": base_rate, "unit": "literal-evals/s", "steps": bs,
+                                  "ms_per_step": ms_b / bs, "launches_per_step": len(insts),
+                                  "speedup_of_batched": value / base_rate},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": "batch_kernel",
+                     "launch_ms": ms / reps,
+                     "model": "gather model: 8 B per literal-eval + 8 B per (variable, restart) + CSR per step"},
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=100)
-    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c3long"])
+    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c3long", "c4"])
+    ap.add_argument("--graph-steps", type=int, default=50, help="c4: steps captured per graph replay")
+    ap.add_argument("--baseline-steps", type=int, default=10, help="c4: steps of per-instance plain launches")
     ap.add_argument("--tile", type=int, default=0, help="restarts per workgroup (0 = auto)")
     ap.add_argument("--block", type=int, default=0, help="threads per workgroup (0 = auto)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -134,6 +203,8 @@ def main():
     from paper_2606_06656_amd import pcls
 
     inst, R, lr, key = workload(args.workload)
+    if args.workload == "c4":
+        return bench_batch(args, inst, R, lr, key)
     prob = pcls.Problem.from_instance(inst, device="cuda:0")
     if args.tile or args.block:
         prob.set_launch(args.tile, args.block)

@@ -174,6 +174,59 @@ int32_t pcls_set_launch(pcls_problem* p, int32_t tile_restarts, int32_t block_th
 int32_t pcls_launch_info(const pcls_problem* p, int32_t R, int32_t* tile_restarts, int32_t* block_threads,
                          int32_t* accumulator_bits, int32_t* grad_scale_log2, size_t* lds_bytes);
 
+/* ------------------------------------------------------------------ batches
+ * Many uploaded problems (instances of uneven size) and their restarts run in
+ * one persistent launch: work items (instance, restart tile) are claimed from a
+ * device counter in order of decreasing cost, and each workgroup runs all steps
+ * of its tile on chip.  Restarts are independent, so no cross-workgroup
+ * synchronisation is needed.  A configuration (threads per workgroup and the
+ * LDS budget the tiles are sized for) can be chosen by pcls_batch_autotune.
+ */
+typedef struct pcls_batch pcls_batch;
+
+typedef struct pcls_batch_config {
+  int32_t block_threads;    /* 256, 512 or 1024 (0 = 1024) */
+  int32_t lds_budget;       /* LDS bytes per workgroup the tiles are sized for (0 = device max) */
+  int32_t wgs_per_cu;       /* cap on persistent workgroups per CU (0 = as many as fit); reports the value used */
+  int32_t accumulator_bits; /* 0 = automatic, 32 or 64; reports the width used */
+} pcls_batch_config;
+
+/*
+ * problems[count]: uploaded plans (borrowed; must outlive the batch);
+ * restarts[count]: R_i >= 1.  *workspace_bytes: device workspace to pass to
+ * pcls_batch_bind (256-byte aligned, caller-owned).
+ */
+int32_t pcls_batch_create(const pcls_problem* const* problems, int32_t count, const int32_t* restarts,
+                          pcls_batch** out, size_t* workspace_bytes);
+/*
+ * Bind device memory: d_x[i] is instance i's state [n_i][round_up(R_i, 64)]
+ * float32; d_trace[i] (or d_trace NULL / entries NULL) receives
+ * [n_steps][R_i] objective values on each pcls_batch_step.  Host arrays are
+ * borrowed for the call.  Applies the current configuration (default on first
+ * bind) and synchronises the stream.  Invalidates a captured graph.
+ */
+int32_t pcls_batch_bind(pcls_batch* b, void* d_workspace, size_t bytes, float* const* d_x, float* const* d_trace,
+                        void* hip_stream);
+int32_t pcls_batch_set_config(pcls_batch* b, const pcls_batch_config* cfg, void* hip_stream);
+int32_t pcls_batch_get_config(const pcls_batch* b, pcls_batch_config* cfg, int32_t* n_items, int32_t* grid);
+/* n_steps projected gradient steps of every instance: one fused launch (plus a counter reset). */
+int32_t pcls_batch_step(pcls_batch* b, float lr, int32_t n_steps, void* hip_stream);
+/*
+ * Capture one pcls_batch_step(lr, n_steps) into a HIP graph (on a private
+ * stream, after synchronising hip_stream); pcls_batch_replay launches it on a
+ * stream.  The graph holds the bound pointers and configuration.
+ */
+int32_t pcls_batch_capture(pcls_batch* b, float lr, int32_t n_steps, void* hip_stream);
+int32_t pcls_batch_replay(pcls_batch* b, void* hip_stream);
+/*
+ * Time every feasible configuration (threads per workgroup x LDS budget) on
+ * probe_steps real steps of the bound states (which advance), keep the fastest.
+ */
+int32_t pcls_batch_autotune(pcls_batch* b, float lr, int32_t probe_steps, void* hip_stream, pcls_batch_config* best,
+                            float* best_ms);
+/* Free the batch (and its graph); never frees caller memory or the problems. */
+int32_t pcls_batch_destroy(pcls_batch* b);
+
 /* Free the host plan; never frees caller memory. */
 int32_t pcls_destroy(pcls_problem* p);
 

@@ -14,7 +14,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libpcls.so")
-SOURCES = ["pcls.hip", "plan.cpp"]
+SOURCES = ["pcls.hip", "plan.cpp", "mpnn.hip"]
 ARCH = os.environ.get("PCLS_OFFLOAD_ARCH", "gfx950")
 
 HIP_FLAGS = [

@@ -392,19 +392,24 @@ __device__ __forceinline__ void run_any_segment(const ProblemDev& P, const Segme
   }
 }
 
-// One workgroup per tile of T = 2^logT restarts; all n_steps steps in LDS.
-// Evaluate mode (obj_out != NULL): one evaluation, writes F and optionally G.
-// Variants by the largest length bucket they handle (a kernel's register
-// allocation covers its longest code path, so short-constraint problems run a
-// variant with fewer registers and more waves per SIMD) and by the width of the
-// fixed-point gradient accumulator (64-bit, or 32-bit where LDS is short).
+// Arguments of one resident tile: restarts [r0, r0 + 2^logT) of one problem.
+struct TileArgs {
+  float* X;          // [n][ldx] state
+  int R, ldx, r0, logT;
+  float lr;
+  int n_steps;
+  float* trace;      // [n_steps][R] or NULL
+  float* obj_out;    // evaluate mode: [R]; NULL = step mode
+  float* g_out;      // evaluate mode: [n][ldx] or NULL
+  float gsc, ginv;   // gradient fixed-point scale 2^S and 2^-S
+  float fsc, finv;   // objective fixed-point scale
+};
+
+// All n_steps steps of one tile with its state in LDS.
 // LDS: x[n][T] float | g[n][T] fixed point | F[T] 64-bit fixed point.
 template <int MAXB, class AT>
-__global__ void __launch_bounds__(1024) tile_kernel(ProblemDev P, float* __restrict__ X, int R, int ldx,
-                                                    int logT, float lr, int n_steps, float* __restrict__ trace,
-                                                    float* __restrict__ obj_out, float* __restrict__ g_out,
-                                                    float gsc, float ginv, float fsc, float finv) {
-  extern __shared__ unsigned long long lds_raw[];
+__device__ __forceinline__ void resident_tile(const ProblemDev& P, const TileArgs& A, unsigned long long* lds_raw) {
+  const int logT = A.logT;
   const int T = 1 << logT;
   const int NT = P.n << logT;
   float* xs = reinterpret_cast<float*>(lds_raw);
@@ -412,49 +417,50 @@ __global__ void __launch_bounds__(1024) tile_kernel(ProblemDev P, float* __restr
   unsigned long long* Fs =
       reinterpret_cast<unsigned long long*>(reinterpret_cast<char*>(gs) + ((size_t)NT * sizeof(AT) + 7) / 8 * 8);
   const int tid = threadIdx.x, nth = blockDim.x;
-  const int r0 = blockIdx.x * T;
+  const int r0 = A.r0, ldx = A.ldx;
   const int t = tid & (T - 1);
-  const bool eval = obj_out != nullptr;
+  const bool eval = A.obj_out != nullptr;
 
   for (int i = tid; i < NT; i += nth) {
     const int v = i >> logT, tt = i & (T - 1);
-    xs[i] = X[(size_t)v * ldx + r0 + tt];
+    xs[i] = A.X[(size_t)v * ldx + r0 + tt];
     gs[i] = 0;
   }
   if (tid < T) Fs[tid] = 0ull;
   __syncthreads();
 
-  for (int s = 0; s < n_steps; ++s) {
+  for (int s = 0; s < A.n_steps; ++s) {
     float facc = 0.f;
     kptr<Segment> segs = kconst(P.segments);
     for (int sg = 0; sg < P.n_segments; ++sg) {
       const Segment S{segs[sg].kind,    segs[sg].bucket, segs[sg].c_begin,   segs[sg].c_count,
                       segs[sg].lit_base, segs[sg].k_fixed, segs[sg].cls_fixed, segs[sg].m_max};
-      run_any_segment<MAXB>(P, S, xs, gs, facc, gsc, tid, nth, logT);
+      run_any_segment<MAXB>(P, S, xs, gs, facc, A.gsc, tid, nth, logT);
     }
     // lanes with equal (lane mod T) hold the same restart
     for (int o = T; o < kWave; o <<= 1) facc += __shfl_xor(facc, o);
-    if ((tid & (kWave - 1)) < T) FixedAcc<unsigned long long>::add(&Fs[t], facc * fsc);
+    if ((tid & (kWave - 1)) < T) FixedAcc<unsigned long long>::add(&Fs[t], facc * A.fsc);
     __syncthreads();
     if (tid < T) {
-      const float F = FixedAcc<unsigned long long>::value(Fs[tid], finv) + P.f_const;
+      const float F = FixedAcc<unsigned long long>::value(Fs[tid], A.finv) + P.f_const;
       Fs[tid] = 0ull;
       const int r = r0 + tid;
-      if (r < R) {
-        if (trace) trace[(size_t)s * R + r] = F;
-        if (eval) obj_out[r] = F;
+      if (r < A.R) {
+        if (A.trace) A.trace[(size_t)s * A.R + r] = F;
+        if (eval) A.obj_out[r] = F;
       }
     }
     if (eval) {
-      if (g_out) {
+      if (A.g_out) {
         for (int i = tid; i < NT; i += nth) {
           const int v = i >> logT, tt = i & (T - 1);
-          g_out[(size_t)v * ldx + r0 + tt] = FixedAcc<AT>::value(gs[i], ginv);
+          A.g_out[(size_t)v * ldx + r0 + tt] = FixedAcc<AT>::value(gs[i], A.ginv);
         }
       }
     } else {
+      const float lr = A.lr;
       for (int i = tid; i < NT; i += nth) {
-        const float xn = fmaf(-lr, FixedAcc<AT>::value(gs[i], ginv), xs[i]);
+        const float xn = fmaf(-lr, FixedAcc<AT>::value(gs[i], A.ginv), xs[i]);
         xs[i] = fminf(1.f, fmaxf(-1.f, xn));
         gs[i] = 0;
       }
@@ -464,9 +470,102 @@ __global__ void __launch_bounds__(1024) tile_kernel(ProblemDev P, float* __restr
   if (!eval) {
     for (int i = tid; i < NT; i += nth) {
       const int v = i >> logT, tt = i & (T - 1);
-      X[(size_t)v * ldx + r0 + tt] = xs[i];
+      A.X[(size_t)v * ldx + r0 + tt] = xs[i];
     }
   }
+}
+
+// One workgroup per tile of T = 2^logT restarts; all n_steps steps in LDS.
+// Evaluate mode (obj_out != NULL): one evaluation, writes F and optionally G.
+// Variants by the largest length bucket they handle (a kernel's register
+// allocation covers its longest code path, so short-constraint problems run a
+// variant with fewer registers and more waves per SIMD) and by the width of the
+// fixed-point gradient accumulator (64-bit, or 32-bit where LDS is short).
+template <int MAXB, class AT>
+__global__ void __launch_bounds__(1024) tile_kernel(ProblemDev P, TileArgs A) {
+  extern __shared__ unsigned long long lds_raw[];
+  A.r0 = blockIdx.x << A.logT;
+  resident_tile<MAXB, AT>(P, A, lds_raw);
+}
+
+// ------------------------------------------------------------ batched engine
+// Many problems (instances) and their restart tiles in one persistent launch.
+// Work items (instance, first restart, tile size) are claimed from a counter in
+// order of decreasing cost; a workgroup keeps claiming until the list is empty.
+
+struct BatchInst {
+  ProblemDev P;
+  float* X;
+  float* trace;
+  int R, ldx;
+  float gsc, ginv, fsc, finv;
+};
+
+struct BatchItem {
+  int inst, r0, logT, pad;
+};
+
+__device__ __forceinline__ ProblemDev load_problem(kptr<BatchInst> bi) {
+  ProblemDev P;
+  P.n = bi->P.n;
+  P.m = bi->P.m;
+  P.L = bi->P.L;
+  P.n_segments = bi->P.n_segments;
+  P.n_classes = bi->P.n_classes;
+  P.f_const = bi->P.f_const;
+  P.segments = bi->P.segments;
+  P.classes = bi->P.classes;
+  P.nodes = bi->P.nodes;
+  P.sp = bi->P.sp;
+  P.litT = bi->P.litT;
+  P.c_k = bi->P.c_k;
+  P.c_cls = bi->P.c_cls;
+  P.c_w = bi->P.c_w;
+  P.row_ptr = bi->P.row_ptr;
+  P.lit = bi->P.lit;
+  P.unit_weights = bi->P.unit_weights;
+  P.max_k = bi->P.max_k;
+  return P;
+}
+
+template <int MAXB, class AT>
+__global__ void __launch_bounds__(1024) batch_kernel(const BatchInst* __restrict__ insts,
+                                                     const BatchItem* __restrict__ items, int n_items,
+                                                     unsigned int* __restrict__ counter, float lr, int n_steps) {
+  extern __shared__ unsigned long long lds_raw[];
+  __shared__ int claimed;
+  for (;;) {
+    if (threadIdx.x == 0) claimed = (int)atomicAdd(counter, 1u);
+    __syncthreads();
+    const int it = claimed;
+    __syncthreads();
+    if (it >= n_items) break;  // every workgroup reaches this once the list is drained
+    kptr<BatchItem> W = kconst(items) + it;
+    kptr<BatchInst> B = kconst(insts) + W->inst;
+    const ProblemDev P = load_problem(B);
+    TileArgs A;
+    A.X = B->X;
+    A.R = B->R;
+    A.ldx = B->ldx;
+    A.r0 = W->r0;
+    A.logT = W->logT;
+    A.lr = lr;
+    A.n_steps = n_steps;
+    A.trace = B->trace;
+    A.obj_out = nullptr;
+    A.g_out = nullptr;
+    A.gsc = B->gsc;
+    A.ginv = B->ginv;
+    A.fsc = B->fsc;
+    A.finv = B->finv;
+    resident_tile<MAXB, AT>(P, A, lds_raw);
+    __syncthreads();
+  }
+}
+
+__global__ void fill_u32_kernel(unsigned int* p, unsigned int v, int count) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < count) p[i] = v;
 }
 
 // ------------------------------------------------------------------- init
@@ -691,25 +790,217 @@ int32_t launch_tile(const pcls_problem* p, int R, float* d_x, float lr, int n_st
   const int R_pad = round_up64(R);
   const int tiles = R_pad >> L.logT;
   const int sg = L.acc64 ? p->s_g64 : p->s_g32;
-  const float gsc = std::ldexp(1.0f, sg), ginv = std::ldexp(1.0f, -sg);
-  const float fsc = std::ldexp(1.0f, p->s_f), finv = std::ldexp(1.0f, -p->s_f);
+  TileArgs A;
+  A.X = d_x;
+  A.R = R;
+  A.ldx = R_pad;
+  A.r0 = 0;
+  A.logT = L.logT;
+  A.lr = lr;
+  A.n_steps = n_steps;
+  A.trace = trace;
+  A.obj_out = obj;
+  A.g_out = grad;
+  A.gsc = std::ldexp(1.0f, sg);
+  A.ginv = std::ldexp(1.0f, -sg);
+  A.fsc = std::ldexp(1.0f, p->s_f);
+  A.finv = std::ldexp(1.0f, -p->s_f);
   if (L.acc64) {
     auto kern = p->max_bucket <= 7 ? tile_kernel<7, unsigned long long>
                                    : (p->max_bucket <= 9 ? tile_kernel<9, unsigned long long>
                                                          : tile_kernel<12, unsigned long long>);
-    hipLaunchKernelGGL(kern, dim3(tiles), dim3(L.block), L.lds, stream, p->dev, d_x, R, R_pad, L.logT, lr, n_steps,
-                       trace, obj, grad, gsc, ginv, fsc, finv);
+    hipLaunchKernelGGL(kern, dim3(tiles), dim3(L.block), L.lds, stream, p->dev, A);
   } else {
     auto kern = p->max_bucket <= 7 ? tile_kernel<7, unsigned int>
                                    : (p->max_bucket <= 9 ? tile_kernel<9, unsigned int> : tile_kernel<12, unsigned int>);
-    hipLaunchKernelGGL(kern, dim3(tiles), dim3(L.block), L.lds, stream, p->dev, d_x, R, R_pad, L.logT, lr, n_steps,
-                       trace, obj, grad, gsc, ginv, fsc, finv);
+    hipLaunchKernelGGL(kern, dim3(tiles), dim3(L.block), L.lds, stream, p->dev, A);
   }
   PCLS_HIP(hipGetLastError(), "tile_kernel launch");
   return PCLS_OK;
 }
 
+// ------------------------------------------------------------ batch (host)
+
+struct BatchState {
+  std::vector<const pcls_problem*> probs;
+  std::vector<int> R;
+  std::vector<float*> x, trace;
+  pcls_batch_config cfg{};
+  bool acc64 = true;
+  int maxb = 0;
+  int n_items = 0;
+  size_t lds = 0;   // dynamic LDS of the persistent launch
+  int grid = 0;
+  void* d_ws = nullptr;
+  size_t ws_bytes = 0;
+  size_t off_inst = 0, off_items = 0, off_counter = 0;
+  std::vector<BatchInst> inst;
+  std::vector<BatchItem> items;
+  hipStream_t cap_stream = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  ~BatchState() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    if (cap_stream) (void)hipStreamDestroy(cap_stream);
+  }
+};
+
+size_t batch_ws_bytes(int count, size_t max_items) {
+  size_t off = 0;
+  auto place = [&](size_t b) {
+    off = (off + 255) / 256 * 256;
+    size_t at = off;
+    off += b;
+    return at;
+  };
+  place(sizeof(BatchInst) * (size_t)count);
+  place(sizeof(BatchItem) * max_items);
+  place(256);
+  return (off + 255) / 256 * 256;
+}
+
+// Tile sizes and work items for a configuration; uploads the tables.
+int32_t batch_configure(BatchState& b, const pcls_batch_config& cfg_in, hipStream_t stream) {
+  DeviceLimits lim;
+  int32_t st = device_limits(lim);
+  if (st != PCLS_OK) return st;
+  pcls_batch_config cfg = cfg_in;
+  if (cfg.block_threads == 0) cfg.block_threads = 1024;
+  if (cfg.block_threads != 256 && cfg.block_threads != 512 && cfg.block_threads != 1024)
+    return set_error(PCLS_E_INVALID, "block_threads %d must be 256, 512 or 1024", cfg.block_threads);
+  // the persistent kernel keeps one claimed-item word in static LDS beside the tiles
+  const int lds_cap = lim.lds_max - 256;
+  if (cfg.lds_budget <= 0 || cfg.lds_budget > lds_cap) cfg.lds_budget = lds_cap;
+  if (cfg.accumulator_bits != 0 && cfg.accumulator_bits != 32 && cfg.accumulator_bits != 64)
+    return set_error(PCLS_E_INVALID, "accumulator_bits must be 0, 32 or 64");
+  const size_t budget = (size_t)cfg.lds_budget;
+  // accumulator: 64-bit unless some instance cannot fit one restart with it
+  bool acc64 = cfg.accumulator_bits != 32;
+  if (cfg.accumulator_bits == 0)
+    for (const pcls_problem* p : b.probs)
+      if (tile_lds_bytes(p->n, 1, 8) > budget) acc64 = false;
+  const int ab = acc64 ? 8 : 4;
+  b.maxb = 0;
+  b.items.clear();
+  b.inst.resize(b.probs.size());
+  size_t lds = 0;
+  struct Cost {
+    double cost;
+    BatchItem it;
+  };
+  std::vector<Cost> work;
+  for (size_t i = 0; i < b.probs.size(); ++i) {
+    const pcls_problem* p = b.probs[i];
+    if (tile_lds_bytes(p->n, 1, ab) > budget)
+      return set_error(PCLS_E_UNSUPPORTED, "instance %zu (%d variables) does not fit the LDS budget of %zu bytes", i,
+                       p->n, budget);
+    if (!acc64 && p->s_g32 < 8)
+      return set_error(PCLS_E_UNSUPPORTED, "instance %zu: weights too large for a 32-bit accumulator", i);
+    b.maxb = std::max(b.maxb, p->max_bucket);
+    const int R_pad = round_up64(b.R[i]);
+    const int tmax_group = kWave / std::max(1, p->max_group);
+    int T = 1;
+    while (T * 2 <= tmax_group && T * 2 <= R_pad && tile_lds_bytes(p->n, T * 2, ab) <= budget) T *= 2;
+    int logT = 0;
+    while ((1 << logT) < T) ++logT;
+    lds = std::max(lds, tile_lds_bytes(p->n, T, ab));
+    for (int r0 = 0; r0 < b.R[i]; r0 += T)
+      work.push_back({(double)p->L * T + (double)p->n * T, BatchItem{(int)i, r0, logT, 0}});
+    BatchInst& I = b.inst[i];
+    I.P = p->dev;
+    I.X = b.x[i];
+    I.trace = b.trace[i];
+    I.R = b.R[i];
+    I.ldx = R_pad;
+    const int sg = acc64 ? p->s_g64 : p->s_g32;
+    I.gsc = std::ldexp(1.0f, sg);
+    I.ginv = std::ldexp(1.0f, -sg);
+    I.fsc = std::ldexp(1.0f, p->s_f);
+    I.finv = std::ldexp(1.0f, -p->s_f);
+  }
+  std::stable_sort(work.begin(), work.end(), [](const Cost& a, const Cost& c) { return a.cost > c.cost; });
+  for (const Cost& w : work) b.items.push_back(w.it);
+  b.n_items = (int)b.items.size();
+  b.acc64 = acc64;
+  b.lds = (lds + 255) / 256 * 256;
+  // persistent workgroups: as many per CU as LDS and 16 resident waves allow
+  int per_cu = std::max(1, (int)((size_t)lim.lds_max / (b.lds + 256)));
+  per_cu = std::min(per_cu, 16 * kWave / cfg.block_threads);
+  if (cfg.wgs_per_cu > 0) per_cu = std::min(per_cu, cfg.wgs_per_cu);
+  b.grid = std::max(1, std::min(b.n_items, per_cu * std::max(1, lim.n_cu)));
+  cfg.wgs_per_cu = per_cu;
+  cfg.accumulator_bits = acc64 ? 64 : 32;
+  b.cfg = cfg;
+  uint8_t* base = (uint8_t*)b.d_ws;
+  PCLS_HIP(hipMemcpyAsync(base + b.off_inst, b.inst.data(), sizeof(BatchInst) * b.inst.size(),
+                          hipMemcpyHostToDevice, stream),
+           "hipMemcpyAsync(batch instances)");
+  PCLS_HIP(hipMemcpyAsync(base + b.off_items, b.items.data(), sizeof(BatchItem) * b.items.size(),
+                          hipMemcpyHostToDevice, stream),
+           "hipMemcpyAsync(batch items)");
+  // the host tables must outlive the asynchronous copies
+  PCLS_HIP(hipStreamSynchronize(stream), "hipStreamSynchronize");
+  if (b.exec) {
+    (void)hipGraphExecDestroy(b.exec);
+    b.exec = nullptr;
+  }
+  if (b.graph) {
+    (void)hipGraphDestroy(b.graph);
+    b.graph = nullptr;
+  }
+  return PCLS_OK;
+}
+
+int32_t batch_launch(BatchState& b, float lr, int n_steps, hipStream_t stream) {
+  uint8_t* base = (uint8_t*)b.d_ws;
+  const BatchInst* insts = (const BatchInst*)(base + b.off_inst);
+  const BatchItem* items = (const BatchItem*)(base + b.off_items);
+  unsigned int* counter = (unsigned int*)(base + b.off_counter);
+  // reset the work counter with a kernel (graph-capturable, no memset node)
+  hipLaunchKernelGGL(fill_u32_kernel, dim3(1), dim3(64), 0, stream, counter, 0u, 1);
+  PCLS_HIP(hipGetLastError(), "fill launch");
+  const dim3 grid(b.grid), block(b.cfg.block_threads);
+  if (b.acc64) {
+    auto k = b.maxb <= 7 ? batch_kernel<7, unsigned long long>
+                         : (b.maxb <= 9 ? batch_kernel<9, unsigned long long> : batch_kernel<12, unsigned long long>);
+    hipLaunchKernelGGL(k, grid, block, b.lds, stream, insts, items, b.n_items, counter, lr, n_steps);
+  } else {
+    auto k = b.maxb <= 7 ? batch_kernel<7, unsigned int>
+                         : (b.maxb <= 9 ? batch_kernel<9, unsigned int> : batch_kernel<12, unsigned int>);
+    hipLaunchKernelGGL(k, grid, block, b.lds, stream, insts, items, b.n_items, counter, lr, n_steps);
+  }
+  PCLS_HIP(hipGetLastError(), "batch_kernel launch");
+  return PCLS_OK;
+}
+
+std::mutex g_batch_attr_mu;
+bool g_batch_attr_set[64] = {false};
+
+int32_t batch_attrs() {
+  int dev = 0;
+  PCLS_HIP(hipGetDevice(&dev), "hipGetDevice");
+  DeviceLimits lim;
+  int32_t st = device_limits(lim);
+  if (st != PCLS_OK) return st;
+  std::lock_guard<std::mutex> lk(g_batch_attr_mu);
+  if (dev >= 0 && dev < 64 && !g_batch_attr_set[dev]) {
+    const void* fs[] = {(const void*)batch_kernel<7, unsigned long long>, (const void*)batch_kernel<9, unsigned long long>,
+                        (const void*)batch_kernel<12, unsigned long long>, (const void*)batch_kernel<7, unsigned int>,
+                        (const void*)batch_kernel<9, unsigned int>, (const void*)batch_kernel<12, unsigned int>};
+    for (const void* f : fs)
+      PCLS_HIP(hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, lim.lds_max),
+               "hipFuncSetAttribute");
+    g_batch_attr_set[dev] = true;
+  }
+  return PCLS_OK;
+}
+
 }  // namespace
+
+struct pcls_batch {
+  BatchState s;
+};
 
 // ======================================================================= C ABI
 
@@ -881,6 +1172,179 @@ int32_t pcls_set_launch(pcls_problem* p, int32_t tile_restarts, int32_t block_th
   p->tile_restarts = tile_restarts;
   p->block_threads = block_threads;
   clear_error();
+  return PCLS_OK;
+}
+
+int32_t pcls_batch_create(const pcls_problem* const* problems, int32_t count, const int32_t* restarts,
+                          pcls_batch** out, size_t* workspace_bytes) {
+  if (!out || !workspace_bytes || !problems || !restarts || count < 1)
+    return set_error(PCLS_E_INVALID, "NULL argument or empty batch");
+  *out = nullptr;
+  size_t max_items = 0;
+  for (int i = 0; i < count; ++i) {
+    if (!problems[i]) return set_error(PCLS_E_INVALID, "problem %d is NULL", i);
+    if (!problems[i]->d_ws) return set_error(PCLS_E_WORKSPACE, "problem %d has no device workspace", i);
+    if (restarts[i] < 1) return set_error(PCLS_E_INVALID, "restarts[%d] must be >= 1", i);
+    max_items += (size_t)restarts[i];
+  }
+  pcls_batch* b = new (std::nothrow) pcls_batch();
+  if (!b) return set_error(PCLS_E_INVALID, "out of host memory");
+  b->s.probs.assign(problems, problems + count);
+  b->s.R.assign(restarts, restarts + count);
+  b->s.x.assign(count, nullptr);
+  b->s.trace.assign(count, nullptr);
+  size_t off = 0;
+  auto place = [&](size_t bytes) {
+    off = (off + 255) / 256 * 256;
+    size_t at = off;
+    off += bytes;
+    return at;
+  };
+  b->s.off_inst = place(sizeof(BatchInst) * (size_t)count);
+  b->s.off_items = place(sizeof(BatchItem) * max_items);
+  b->s.off_counter = place(256);
+  b->s.ws_bytes = batch_ws_bytes(count, max_items);
+  *out = b;
+  *workspace_bytes = b->s.ws_bytes;
+  clear_error();
+  return PCLS_OK;
+}
+
+int32_t pcls_batch_bind(pcls_batch* b, void* d_ws, size_t bytes, float* const* d_x, float* const* d_trace,
+                        void* stream) {
+  if (!b || !d_x) return set_error(PCLS_E_INVALID, "NULL argument");
+  if (!d_ws || bytes < b->s.ws_bytes || ((uintptr_t)d_ws & 255u))
+    return set_error(PCLS_E_WORKSPACE, "batch workspace missing, misaligned or smaller than %zu bytes", b->s.ws_bytes);
+  for (size_t i = 0; i < b->s.probs.size(); ++i) {
+    if (!d_x[i]) return set_error(PCLS_E_INVALID, "state %zu is NULL", i);
+    b->s.x[i] = d_x[i];
+    b->s.trace[i] = d_trace ? d_trace[i] : nullptr;
+  }
+  b->s.d_ws = d_ws;
+  int32_t st = batch_attrs();
+  if (st != PCLS_OK) return st;
+  st = batch_configure(b->s, b->s.cfg, (hipStream_t)stream);
+  if (st == PCLS_OK) clear_error();
+  return st;
+}
+
+int32_t pcls_batch_set_config(pcls_batch* b, const pcls_batch_config* cfg, void* stream) {
+  if (!b || !cfg) return set_error(PCLS_E_INVALID, "NULL argument");
+  if (!b->s.d_ws) return set_error(PCLS_E_WORKSPACE, "batch is not bound (call pcls_batch_bind)");
+  int32_t st = batch_configure(b->s, *cfg, (hipStream_t)stream);
+  if (st == PCLS_OK) clear_error();
+  return st;
+}
+
+int32_t pcls_batch_get_config(const pcls_batch* b, pcls_batch_config* cfg, int32_t* n_items, int32_t* grid) {
+  if (!b) return set_error(PCLS_E_INVALID, "NULL argument");
+  if (cfg) *cfg = b->s.cfg;
+  if (n_items) *n_items = b->s.n_items;
+  if (grid) *grid = b->s.grid;
+  clear_error();
+  return PCLS_OK;
+}
+
+int32_t pcls_batch_step(pcls_batch* b, float lr, int32_t n_steps, void* stream) {
+  if (!b) return set_error(PCLS_E_INVALID, "NULL argument");
+  if (!b->s.d_ws) return set_error(PCLS_E_WORKSPACE, "batch is not bound (call pcls_batch_bind)");
+  if (n_steps < 0 || !(lr == lr)) return set_error(PCLS_E_INVALID, "bad n_steps or lr");
+  if (n_steps == 0) return PCLS_OK;
+  int32_t st = batch_launch(b->s, lr, n_steps, (hipStream_t)stream);
+  if (st == PCLS_OK) clear_error();
+  return st;
+}
+
+int32_t pcls_batch_capture(pcls_batch* b, float lr, int32_t n_steps, void* stream) {
+  if (!b) return set_error(PCLS_E_INVALID, "NULL argument");
+  if (!b->s.d_ws) return set_error(PCLS_E_WORKSPACE, "batch is not bound (call pcls_batch_bind)");
+  if (n_steps < 1 || !(lr == lr)) return set_error(PCLS_E_INVALID, "bad n_steps or lr");
+  BatchState& s = b->s;
+  if (!s.cap_stream) PCLS_HIP(hipStreamCreateWithFlags(&s.cap_stream, hipStreamNonBlocking), "hipStreamCreate");
+  // order the capture after work already queued on the caller's stream
+  PCLS_HIP(hipStreamSynchronize((hipStream_t)stream), "hipStreamSynchronize");
+  if (s.exec) {
+    (void)hipGraphExecDestroy(s.exec);
+    s.exec = nullptr;
+  }
+  if (s.graph) {
+    (void)hipGraphDestroy(s.graph);
+    s.graph = nullptr;
+  }
+  PCLS_HIP(hipStreamBeginCapture(s.cap_stream, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
+  int32_t st = batch_launch(s, lr, n_steps, s.cap_stream);
+  hipGraph_t g = nullptr;
+  hipError_t e = hipStreamEndCapture(s.cap_stream, &g);
+  if (st != PCLS_OK) {
+    if (g) (void)hipGraphDestroy(g);
+    return st;
+  }
+  if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+  s.graph = g;
+  PCLS_HIP(hipGraphInstantiate(&s.exec, s.graph, nullptr, nullptr, 0), "hipGraphInstantiate");
+  clear_error();
+  return PCLS_OK;
+}
+
+int32_t pcls_batch_replay(pcls_batch* b, void* stream) {
+  if (!b) return set_error(PCLS_E_INVALID, "NULL argument");
+  if (!b->s.exec) return set_error(PCLS_E_INVALID, "no captured graph (call pcls_batch_capture)");
+  PCLS_HIP(hipGraphLaunch(b->s.exec, (hipStream_t)stream), "hipGraphLaunch");
+  clear_error();
+  return PCLS_OK;
+}
+
+int32_t pcls_batch_autotune(pcls_batch* b, float lr, int32_t probe_steps, void* stream, pcls_batch_config* best,
+                            float* best_ms) {
+  if (!b || probe_steps < 1) return set_error(PCLS_E_INVALID, "NULL batch or probe_steps < 1");
+  if (!b->s.d_ws) return set_error(PCLS_E_WORKSPACE, "batch is not bound (call pcls_batch_bind)");
+  DeviceLimits lim;
+  int32_t st = device_limits(lim);
+  if (st != PCLS_OK) return st;
+  hipStream_t s = (hipStream_t)stream;
+  hipEvent_t e0, e1;
+  PCLS_HIP(hipEventCreate(&e0), "hipEventCreate");
+  PCLS_HIP(hipEventCreate(&e1), "hipEventCreate");
+  const int blocks[] = {256, 512, 1024};
+  const int budgets[] = {lim.lds_max, lim.lds_max / 2, lim.lds_max / 3, lim.lds_max / 4};
+  pcls_batch_config win{};
+  float win_ms = 0.f;
+  bool have = false;
+  for (int bt : blocks) {
+    for (int bud : budgets) {
+      pcls_batch_config c{};
+      c.block_threads = bt;
+      c.lds_budget = bud;
+      c.accumulator_bits = b->s.cfg.accumulator_bits == 32 ? 32 : 0;
+      if (batch_configure(b->s, c, s) != PCLS_OK) continue;  // infeasible budget
+      if (batch_launch(b->s, lr, 1, s) != PCLS_OK) continue;  // warm-up
+      (void)hipEventRecord(e0, s);
+      st = batch_launch(b->s, lr, probe_steps, s);
+      (void)hipEventRecord(e1, s);
+      if (st != PCLS_OK) continue;
+      if (hipEventSynchronize(e1) != hipSuccess) continue;
+      float ms = 0.f;
+      (void)hipEventElapsedTime(&ms, e0, e1);
+      if (!have || ms < win_ms) {
+        win = b->s.cfg;
+        win_ms = ms;
+        have = true;
+      }
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (!have) return set_error(PCLS_E_UNSUPPORTED, "no feasible batch configuration");
+  st = batch_configure(b->s, win, s);
+  if (st != PCLS_OK) return st;
+  if (best) *best = b->s.cfg;
+  if (best_ms) *best_ms = win_ms;
+  clear_error();
+  return PCLS_OK;
+}
+
+int32_t pcls_batch_destroy(pcls_batch* b) {
+  delete b;
   return PCLS_OK;
 }
 

@@ -23,7 +23,10 @@ STATUS_NAMES = {0: "PCLS_OK", 1: "PCLS_E_INVALID", 2: "PCLS_E_UNSUPPORTED", 3: "
 # exported entry points (checked by the CPU test suite against include/pcls.h)
 EXPORTS = ["pcls_plan", "pcls_plan_ex", "pcls_problem_info", "pcls_upload", "pcls_init_restarts",
            "pcls_evaluate", "pcls_step", "pcls_extract", "pcls_set_launch", "pcls_launch_info",
-           "pcls_destroy", "pcls_last_error"]
+           "pcls_destroy", "pcls_last_error",
+           "pcls_batch_create", "pcls_batch_bind", "pcls_batch_set_config", "pcls_batch_get_config",
+           "pcls_batch_step", "pcls_batch_capture", "pcls_batch_replay", "pcls_batch_autotune",
+           "pcls_batch_destroy"]
 
 
 class PclsError(RuntimeError):

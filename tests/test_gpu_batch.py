@@ -1,0 +1,151 @@
+"""Batched persistent engine: many uneven instances in one launch, hipGraph
+capture/replay and the autotuner, checked against per-instance launches.
+
+Gradients accumulate in exact, order-independent fixed point, so every restart's
+trajectory depends only on its own state: batched and per-instance runs must
+agree bitwise on the states, whatever tiles and workgroup shapes each uses."""
+import os
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+from paper_2606_06656_amd import pcls, synth  # noqa: E402
+from paper_2606_06656_amd.batch import Batch  # noqa: E402
+from gpu_util import log, oracle_for, rows_of  # noqa: E402
+from oracle import native as N  # noqa: E402
+
+
+def make_instances(count=10, seed=0):
+    rng = np.random.default_rng(seed)
+    out = []
+    for i in range(count):
+        n = int(rng.integers(30, 3000))
+        if i % 3 == 0:
+            inst = synth.random_ksat(n, int(4.2 * n), 3, seed=seed * 100 + i)
+        elif i % 3 == 1:
+            inst = synth.c2_mixed(seed=seed * 100 + i, n=n, n_or=3 * n, n_xor=n // 10, n_card=n // 20)
+        else:
+            inst = synth.mixed_small(n=max(n, 80), seed=seed * 100 + i, kmax=40, count=2 * n)
+        out.append(inst)
+    return out
+
+
+def setup(count=10, seed=0, R_list=None):
+    insts = make_instances(count, seed)
+    probs = [pcls.Problem.from_instance(i) for i in insts]
+    R_list = R_list or [int(r) for r in np.random.default_rng(seed + 1).choice([1, 33, 64, 100, 128], count)]
+    states = []
+    for k, (p, R) in enumerate(zip(probs, R_list)):
+        X = p.new_state(R)
+        p.init_restarts(X, R, 1000 + k)
+        states.append(X)
+    return insts, probs, R_list, states
+
+
+def test_batch_equals_per_instance_bitwise():
+    insts, probs, Rs, states = setup(10, 0)
+    log(f"case batch R={Rs} n={[i.n for i in insts]}")
+    ref_states = [X.clone() for X in states]
+    traces = [torch.zeros((4, R), device=X.device) for R, X in zip(Rs, states)]
+    b = Batch(probs, Rs, states, traces)
+    cfg = b.config()
+    assert cfg["n_items"] >= len(probs) and cfg["grid"] >= 1
+    b.step(0.1, 4)
+    for p, R, X in zip(probs, Rs, ref_states):
+        p.step(X, R, 0.1, 4)
+    torch.cuda.synchronize()
+    for k, (X, Y) in enumerate(zip(states, ref_states)):
+        assert torch.equal(X, Y), f"instance {k}"
+    # the trace holds F at the iterates before each step
+    for k in (0, 4, 9):
+        p, R = probs[k], Rs[k]
+        Z = p.new_state(R)
+        p.init_restarts(Z, R, 1000 + k)
+        for s in range(4):
+            obj, _ = p.evaluate(Z, R, want_grad=False)
+            np.testing.assert_allclose(traces[k][s].cpu().numpy(), obj.cpu().numpy(), rtol=1e-6, atol=1e-4)
+            p.step(Z, R, 0.1, 1)
+
+
+def test_batch_objective_matches_oracle():
+    insts, probs, Rs, states = setup(5, 3, [64, 17, 100, 64, 1])
+    log("case batch oracle")
+    traces = [torch.zeros((1, R), device=X.device) for R, X in zip(Rs, states)]
+    x0 = [rows_of(X, R) for X, R in zip(states, Rs)]
+    b = Batch(probs, Rs, states, traces)
+    b.step(0.1, 1)
+    for k, inst in enumerate(insts):
+        ref = oracle_for(inst).evaluate(x0[k], method=N.PMF, want_grad=False)
+        sF = inst.m
+        err = np.abs(traces[k][0].cpu().numpy() - ref["obj"])
+        assert np.all(err <= 1e-5 * np.maximum(np.abs(ref["obj"]), sF)), k
+
+
+def test_graph_capture_replay():
+    insts, probs, Rs, states = setup(8, 5)
+    log("case batch graph")
+    eager = [X.clone() for X in states]
+    b = Batch(probs, Rs, states)
+    be = Batch(probs, Rs, eager)
+    b.capture(0.1, 3)
+    for rep in range(3):
+        b.replay()
+        be.step(0.1, 3)
+        torch.cuda.synchronize()
+        # eager work of the program between replays
+        _ = [X.sum().item() for X in states]
+        for k, (X, Y) in enumerate(zip(states, eager)):
+            assert torch.equal(X, Y), f"replay {rep} instance {k}"
+
+
+def test_autotune_and_cache(tmp_path):
+    insts, probs, Rs, states = setup(6, 7)
+    log("case batch autotune")
+    before = [X.clone() for X in states]
+    b = Batch(probs, Rs, states)
+    cache = os.path.join(str(tmp_path), "tune.json")
+    res = b.autotune(0.1, probe_steps=2, cache_path=cache)
+    assert res["block_threads"] in (256, 512, 1024) and not res["cached"]
+    for X, Y in zip(states, before):
+        assert torch.equal(X, Y)  # timing ran on scratch copies
+    res2 = b.autotune(0.1, probe_steps=2, cache_path=cache)
+    assert res2["cached"] and res2["block_threads"] == res["block_threads"]
+    ref = [X.clone() for X in states]
+    b.step(0.1, 2)
+    for p, R, X in zip(probs, Rs, ref):
+        p.step(X, R, 0.1, 2)
+    for X, Y in zip(states, ref):
+        assert torch.equal(X, Y)
+
+
+@pytest.mark.parametrize("block,budget", [(256, 40 * 1024), (512, 80 * 1024), (1024, 0)])
+def test_batch_configs_agree(block, budget):
+    insts, probs, Rs, states = setup(6, 9, [64, 64, 33, 128, 5, 64])
+    log(f"case batch config {block} {budget}")
+    ref = [X.clone() for X in states]
+    b = Batch(probs, Rs, states)
+    try:
+        b.set_config(block, budget)
+    except pcls.PclsError as e:
+        assert e.status == pcls.PCLS_E_UNSUPPORTED
+        pytest.skip("an instance does not fit this LDS budget")
+    b.step(0.05, 3)
+    for p, R, X in zip(probs, Rs, ref):
+        p.step(X, R, 0.05, 3)
+    for X, Y in zip(states, ref):
+        assert torch.equal(X, Y)
+
+
+def test_batch_errors():
+    insts, probs, Rs, states = setup(2, 11, [4, 4])
+    b = Batch(probs, Rs, states)
+    with pytest.raises(pcls.PclsError):
+        b.set_config(block_threads=300)
+    with pytest.raises(pcls.PclsError):
+        b.replay()  # nothing captured
+    with pytest.raises(pcls.PclsError):
+        Batch(probs, [4, 0])
