@@ -166,6 +166,34 @@ def bench_batch(args, insts, R, lr, key):
     print(json.dumps(out), flush=True)
 
 
+WEIGHTS = os.path.join(ROOT, "paper_2606_06656_amd", "weights", "mpnn_3sat.npz")
+
+
+def learned_vs_random(count=16, n=200, budgets=(0, 10, 50), R=64):
+    """Second half of the metric: satisfied-constraint fraction of learned versus
+    uniform restarts at equal step budgets on held-out random 3-SAT (ratio 4.2),
+    using the committed network weights; None if no weights are committed."""
+    if not os.path.exists(WEIGHTS):
+        return None
+    from paper_2606_06656_amd import learned as LRN
+    from paper_2606_06656_amd import synth
+    P, meta = LRN.Params.load(WEIGHTS, "cuda:0")
+    insts = [synth.c5_eval(n, i) for i in range(count)]
+    lrn = LRN.sat_fraction_curves(insts, list(budgets), R=R, seed=20000, P=P, gamma=meta["gamma"],
+                                  sigma=meta["sigma"])
+    uni = LRN.sat_fraction_curves(insts, list(budgets), R=R, seed=20000, P=None)
+    rows = []
+    for bi, S in enumerate(budgets):
+        d = lrn["mean"][:, bi] - uni["mean"][:, bi]
+        m, lo, hi = LRN.paired_bootstrap_ci(d, seed=S)
+        rows.append({"steps": S, "sat_rate_learned": float(lrn["mean"][:, bi].mean()),
+                     "sat_rate_random": float(uni["mean"][:, bi].mean()), "gain": m, "gain_ci95": [lo, hi],
+                     "best_of_R_learned": float(lrn["best"][:, bi].mean()),
+                     "best_of_R_random": float(uni["best"][:, bi].mean())})
+    return {"instances": count, "n": n, "ratio": 4.2, "restarts": R, "statistic": "mean over restarts",
+            "budgets": rows}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -178,6 +206,7 @@ def main():
     ap.add_argument("--block", type=int, default=0, help="threads per workgroup (0 = auto)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=12.0)
+    ap.add_argument("--no-learned", action="store_true", help="skip the learned-vs-random restart comparison")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run 5 device copies of MIB MiB (scales the HBM byte counters)")
     args = ap.parse_args()
@@ -251,6 +280,8 @@ def main():
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(inst, lr, args.cpu_budget)
+    if args.workload == "c2" and not args.no_learned:
+        out["learned_init"] = learned_vs_random()
     print(json.dumps(out), flush=True)
 
 

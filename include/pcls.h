@@ -17,8 +17,11 @@
  *  - A symmetric constraint's value at a corner is -1 when it holds and +1
  *    when it is violated; a corner satisfies the formula iff sum_c FE_c = -m.
  *  - Restart state X is float32, laid out [n][R_pad] (restart index
- *    contiguous), R_pad = round_up(R, 64).  Columns r >= R are padding the
- *    library may read and write.
+ *    contiguous), R_pad = round_up(R, 64).  Columns r >= R are padding: the
+ *    library may read and write them and their content is unspecified.
+ *  - Gradients and objectives are accumulated in exact fixed point, so results
+ *    are bitwise reproducible and independent of launch shape; the fixed-point
+ *    scales are chosen per problem (see pcls_info) so that no sum overflows.
  *  - All device pointers are caller-owned (hipMalloc'd or torch tensors).
  *    Every device operation is enqueued asynchronously on the given HIP
  *    stream (hipStream_t passed as void*; NULL = the null stream); the host
@@ -145,6 +148,30 @@ int32_t pcls_evaluate(const pcls_problem* p, int32_t R, const float* d_x, float*
  */
 int32_t pcls_step(const pcls_problem* p, int32_t R, float* d_x, float lr, int32_t n_steps,
                   float* d_obj_trace, void* hip_stream);
+
+/*
+ * Options of pcls_step_ex (zero-initialised = plain pcls_step).
+ *  d_fixed : device int8 [n] or NULL.  0 = free; -1 / +1 = variable held at
+ *            True / False in every restart (its x is set on entry and after
+ *            every step): completion of a partial assignment (paper: Case
+ *            Studies, "Hard Random 3-SAT: Partial Assignment Completion").
+ *  tol     : > 0 enables the convergence test max_v |x_{s+1} - x_s| < tol per
+ *            restart.  A workgroup's restarts stop stepping once all of them
+ *            have converged (converged restarts stop costing compute: Case
+ *            Studies, "Costas Arrays"); trace entries after that repeat the
+ *            last evaluated objective.  0 = no test.
+ *  d_iters : device int32 [R] or NULL: 1-based step at which the restart first
+ *            passed the test, n_steps if it never did (requires tol > 0).
+ */
+typedef struct pcls_step_options {
+  const int8_t* d_fixed;
+  float tol;
+  int32_t* d_iters;
+  int32_t reserved[4];
+} pcls_step_options;
+
+int32_t pcls_step_ex(const pcls_problem* p, int32_t R, float* d_x, float lr, int32_t n_steps, float* d_obj_trace,
+                     const pcls_step_options* options, void* hip_stream);
 
 /*
  * Round X to corners and count violated constraints exactly.

@@ -35,8 +35,10 @@ int32_t pcls_mpnn_gemm(const float* A, int32_t lda, int32_t N, int32_t K, const 
                        void* hip_stream);
 
 /* dW[M x K] = (accumulate ? dW : 0) + sum_n dZ[n][m] X[n][k] (row strides ldz, ldx);
- * M, K multiples of 16.  scratch: device float buffer of pcls_mpnn_gemm_tn_scratch
- * bytes (per-chunk partial sums, reduced in a fixed order). */
+ * M, K multiples of 16.  Operands are split into bf16 high and low parts and the
+ * products hi*hi + hi*lo + lo*hi accumulated in float32 (about 16 bits of operand
+ * precision).  scratch: device float buffer of pcls_mpnn_gemm_tn_scratch bytes
+ * (per-chunk partial sums, reduced in a fixed order). */
 size_t pcls_mpnn_gemm_tn_scratch(int32_t N, int32_t M, int32_t K);
 int32_t pcls_mpnn_gemm_tn(const float* dZ, int32_t ldz, const float* X, int32_t ldx, int32_t N, int32_t M, int32_t K,
                           float* dW, int32_t accumulate, float* scratch, size_t scratch_bytes, void* hip_stream);

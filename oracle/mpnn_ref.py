@@ -12,8 +12,11 @@ Definition (hidden width 64, three rounds):
                  h_v' = relu(W2 h_v + bv + (1/deg_v) sum_{(c,i): v_i = v} U_{s_i} h_c')
     with W_{+} = Wpn[:64], W_{-} = Wpn[64:], U likewise from Upn;
     x_hat = tanh(wo . h_v + bo).
-Optionally every matrix-product input is rounded to bf16 (round to nearest
-even), the precision at which the GPU kernels feed their matrix cores.
+Optionally the products follow the mixed-precision scheme of the GPU kernels:
+forward operands rounded to bf16 (round to nearest even); in the backward pass
+the input gradient multiplies the bf16-rounded output gradient by the bf16
+weights, and the weight gradient is taken at full precision from the unrounded
+activations. All other arithmetic stays in FP64.
 """
 from __future__ import annotations
 
@@ -25,6 +28,26 @@ HID, FEAT, LAYERS = 64, 32, 3
 
 def bf16(x: torch.Tensor) -> torch.Tensor:
     return x.to(torch.bfloat16).to(torch.float64)
+
+
+class _Bf16Linear(torch.autograd.Function):
+    """y = bf16(x) bf16(W)^T with the backward pass described in the header."""
+
+    @staticmethod
+    def forward(ctx, x, W):
+        ctx.save_for_backward(x, W)
+        return bf16(x) @ bf16(W).T
+
+    @staticmethod
+    def backward(ctx, dy):
+        x, W = ctx.saved_tensors
+        return bf16(dy) @ bf16(W), dy.T @ x
+
+
+def _linear(emulate_bf16):
+    if emulate_bf16:
+        return _Bf16Linear.apply
+    return lambda x, W: x @ W.T
 
 
 def spec():
@@ -67,7 +90,7 @@ def features(n, row_ptr, lit, ctype, param):
 
 def forward(instances, params, emulate_bf16=False):
     """x_hat for the disjoint union of instances (each: n, row_ptr, lit, ctype, param)."""
-    r = bf16 if emulate_bf16 else (lambda t: t)
+    lin = _linear(emulate_bf16)
     fvs, fcs, cons, vars_, signs = [], [], [], [], []
     voff = coff = 0
     for (n, row_ptr, lit, ctype, param) in instances:
@@ -88,18 +111,18 @@ def forward(instances, params, emulate_bf16=False):
     Nv, Nc = Fv.shape[0], Fc.shape[0]
     k = torch.zeros(Nc, dtype=torch.float64).index_add_(0, con, torch.ones(len(cons), dtype=torch.float64))
     deg = torch.zeros(Nv, dtype=torch.float64).index_add_(0, var, torch.ones(len(vars_), dtype=torch.float64))
-    W = {name: (r(p) if p.dim() == 2 else p) for name, p in params.items()}
-    hv = torch.relu(r(Fv) @ W["Ev"].T + params["ev"])
-    hc = torch.relu(r(Fc) @ W["Ec"].T + params["ec"])
+    hv = torch.relu(lin(Fv, params["Ev"]) + params["ev"])
+    hc = torch.relu(lin(Fc, params["Ec"]) + params["ec"])
     for l in range(LAYERS):
-        Wp, Wn = W[f"Wpn_{l}"][:HID], W[f"Wpn_{l}"][HID:]
-        msg_src = torch.where(pos[:, None], r(hv)[var] @ Wp.T, r(hv)[var] @ Wn.T)
+        # [W_+; W_-] h_v for every variable, then the sign-selected half per literal
+        Pm = lin(hv, params[f"Wpn_{l}"])
+        msg_src = torch.where(pos[:, None], Pm[var, :HID], Pm[var, HID:])
         msg = torch.zeros(Nc, HID, dtype=torch.float64).index_add(0, con, msg_src) / k.clamp(min=1)[:, None]
-        hc = torch.relu(r(hc) @ W[f"W1_{l}"].T + params[f"bc_{l}"] + msg)
-        Up, Un = W[f"Upn_{l}"][:HID], W[f"Upn_{l}"][HID:]
-        back_src = torch.where(pos[:, None], r(hc)[con] @ Up.T, r(hc)[con] @ Un.T)
+        hc = torch.relu(lin(hc, params[f"W1_{l}"]) + params[f"bc_{l}"] + msg)
+        Qm = lin(hc, params[f"Upn_{l}"])
+        back_src = torch.where(pos[:, None], Qm[con, :HID], Qm[con, HID:])
         back = torch.zeros(Nv, HID, dtype=torch.float64).index_add(0, var, back_src) / deg.clamp(min=1)[:, None]
-        hv = torch.relu(r(hv) @ W[f"W2_{l}"].T + params[f"bv_{l}"] + back)
+        hv = torch.relu(lin(hv, params[f"W2_{l}"]) + params[f"bv_{l}"] + back)
     return torch.tanh(hv @ params["wo"] + params["bo"])
 
 

@@ -25,6 +25,7 @@ enum Kind : int32_t { KIND_PROD1 = 0, KIND_PROD2 = 1, KIND_DFT = 2, KIND_CONST =
 constexpr int kNumBuckets = 13;
 constexpr int kBucketKmax[kNumBuckets] = {1, 2, 3, 4, 5, 6, 7, 8, 16, 32, 64, 128, 256};
 constexpr int kMaxK = 256;
+constexpr int kMaxSegments = 3 * kNumBuckets;  // (kind, bucket) pairs
 
 // Lanes per (constraint, restart) pair: one lane holds up to 16 literals of a
 // product kind or 8 of the DFT kind (register budget at 4 waves per SIMD);
@@ -89,6 +90,7 @@ struct ProblemDev {
   const int32_t* lit;            // planned-order literal codes
   int32_t unit_weights;          // all weights 1.0
   int32_t max_k;
+  const int32_t* occ;            // per variable: occurrences in non-constant constraints
 };
 
 }  // namespace pcls

@@ -23,6 +23,7 @@ int32_t fail(int32_t code, const char* what) {
 
 int32_t hip_check(hipError_t e, const char* what) {
   if (e == hipSuccess) return 0;
+  (void)hipGetLastError();  // clear the sticky error
   g_err = std::string(what) + ": " + hipGetErrorString(e);
   return 5;
 }
@@ -106,6 +107,10 @@ __global__ void __launch_bounds__(256) gemm_kernel(const float* __restrict__ A, 
 
 // dW[M x K] (+)= sum_n dZ[n][m] X[n][k]: one wave per 16x16 output tile and
 // chunk of rows; chunk partials are summed in a second pass (deterministic).
+// Both operands are split into bf16 high and low parts (x = hi + lo) and the
+// three significant cross products are accumulated: a weight gradient is a
+// long sum over rows that may cancel, so it gets about 16 bits of operand
+// precision instead of 8.
 __global__ void __launch_bounds__(64) gemm_tn_kernel(const float* __restrict__ dZ, int ldz,
                                                      const float* __restrict__ X, int ldx, int N, int M, int K,
                                                      int rows_per_chunk, float* __restrict__ partial) {
@@ -118,14 +123,20 @@ __global__ void __launch_bounds__(64) gemm_tn_kernel(const float* __restrict__ d
   const int n_begin = chunk * rows_per_chunk, n_end = min(N, n_begin + rows_per_chunk);
   floatx4 acc = {0.f, 0.f, 0.f, 0.f};
   for (int n0 = n_begin; n0 < n_end; n0 += 32) {
-    Pack8 a, b;
+    Pack8 ah, al, bh, bl;
 #pragma unroll
     for (int e = 0; e < 8; ++e) {
       const int n = n0 + nq + e;
-      a.u[e] = n < n_end ? f2bf(dZ[(size_t)n * ldz + m]) : (uint16_t)0;
-      b.u[e] = n < n_end ? f2bf(X[(size_t)n * ldx + k]) : (uint16_t)0;
+      const float za = n < n_end ? dZ[(size_t)n * ldz + m] : 0.f;
+      const float xb = n < n_end ? X[(size_t)n * ldx + k] : 0.f;
+      ah.u[e] = f2bf(za);
+      al.u[e] = f2bf(za - bf2f(ah.u[e]));
+      bh.u[e] = f2bf(xb);
+      bl.u[e] = f2bf(xb - bf2f(bh.u[e]));
     }
-    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a.v, b.v, acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah.v, bh.v, acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah.v, bl.v, acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al.v, bh.v, acc, 0, 0, 0);
   }
   float* out = partial + (size_t)chunk * M * K;
 #pragma unroll

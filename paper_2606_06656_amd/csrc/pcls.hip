@@ -62,13 +62,19 @@ struct FixedAcc;
 
 template <>
 struct FixedAcc<unsigned long long> {
-  // |v| < 2^51: 1.5 * 2^52 + v rounds v to the nearest integer in the FP64
-  // significand, whose low bits then hold it in two's complement.
+  // |v| < 2^51: the FP64 sum 1.5 * 2^52 + v rounds v to the nearest integer,
+  // and its bit pattern is kMagic + rint(v).  Gradient terms add the raw bit
+  // patterns; a variable receives exactly one term per occurrence per step, so
+  // value() removes count * kMagic once (all arithmetic mod 2^64 is exact).
+  static constexpr unsigned long long kMagic = 0x4338000000000000ull;
   static __device__ __forceinline__ void add(unsigned long long* p, float v) {
-    const long long q = __double_as_longlong((double)v + 6755399441055744.0) - 0x4338000000000000LL;
-    atomicAdd(p, (unsigned long long)q);
+    atomicAdd(p, (unsigned long long)__double_as_longlong((double)v + 6755399441055744.0));
   }
-  static __device__ __forceinline__ float value(unsigned long long a, float inv) {
+  static __device__ __forceinline__ float value(unsigned long long a, float inv, int count) {
+    return (float)((double)(long long)(a - (unsigned long long)count * kMagic) * (double)inv);
+  }
+  // objective sums: integers with the magic already removed (fixed_term)
+  static __device__ __forceinline__ float value_exact(unsigned long long a, float inv) {
     return (float)((double)(long long)a * (double)inv);
   }
 };
@@ -78,8 +84,15 @@ struct FixedAcc<unsigned int> {
   static __device__ __forceinline__ void add(unsigned int* p, float v) {
     atomicAdd(p, (unsigned int)__float2int_rn(v));
   }
-  static __device__ __forceinline__ float value(unsigned int a, float inv) { return (float)(int)a * inv; }
+  static __device__ __forceinline__ float value(unsigned int a, float inv, int) { return (float)(int)a * inv; }
 };
+
+// One objective term rounded to an integer (|v| < 2^51): per-lane sums of
+// these are exact, so the objective does not depend on which lane took which
+// constraint.
+__device__ __forceinline__ long long fixed_term(float v) {
+  return __double_as_longlong((double)v + 6755399441055744.0) - 0x4338000000000000LL;
+}
 
 // ---------------------------------------------------------------- group scans
 // The G lanes of one (constraint, restart) pair sit at stride T in the wave:
@@ -177,8 +190,8 @@ __device__ __forceinline__ ProdParams prod_params(kptr<ClassRec> classes, int cl
 
 template <int NN, int KMAX, int G, class AT>
 __device__ __forceinline__ void prod_pair(const ProblemDev& P, const Segment& S, int c_local, int lig, int t,
-                                          int logT, const float* xs, AT* gs, float& facc, float gsc,
-                                          const PairCtx& q, const ProdParams& pp) {
+                                          int logT, const float* xs, AT* gs, long long& facc, float gsc,
+                                          float fsc, const PairCtx& q, const ProdParams& pp) {
   constexpr int J = KMAX / G;
   constexpr bool kExact = KMAX <= 8;  // buckets up to 8 hold a single length
   const int T = 1 << logT;
@@ -223,7 +236,7 @@ __device__ __forceinline__ void prod_pair(const ProblemDev& P, const Segment& S,
   if (lig == 0) {
     float fe = c1 * (run1 * xq1);
     if constexpr (NN == 2) fe = fmaf(c2, run2 * xq2, fe);
-    facc = fmaf(q.w, fe, facc);
+    facc += fixed_term(q.w * fsc * fe);
   }
   const float s1 = c1 * b1 * (q.w * gsc) * xp1;
   const float s2 = -0.5f * c2 * (q.w * gsc) * xp2;
@@ -244,8 +257,8 @@ __device__ __forceinline__ void prod_pair(const ProblemDev& P, const Segment& S,
 // dFE/dy_i = sum_m Re(2 chat_m beta_m prod_{j != i}(alpha_m + beta_m y_j)) [+ chat_{K/2} prod_{j != i} y_j].
 template <int KMAX, int G, class AT>
 __device__ __forceinline__ void dft_pair(const ProblemDev& P, const Segment& S, int c_local, int lig, int t,
-                                         int logT, const float* xs, AT* gs, float& facc, float gsc,
-                                         const PairCtx& q) {
+                                         int logT, const float* xs, AT* gs, long long& facc, float gsc,
+                                         float fsc, const PairCtx& q) {
   constexpr int J = KMAX / G;
   constexpr bool kExact = KMAX <= 8;
   const int T = 1 << logT;
@@ -321,7 +334,7 @@ __device__ __forceinline__ void dft_pair(const ProblemDev& P, const Segment& S, 
       }
     }
   }
-  if (lig == 0) facc = fmaf(q.w, fe, facc);
+  if (lig == 0) facc += fixed_term(q.w * fsc * fe);
 #pragma unroll
   for (int j = 0; j < J; ++j) {
     if (addr[j] >= 0) {
@@ -331,31 +344,42 @@ __device__ __forceinline__ void dft_pair(const ProblemDev& P, const Segment& S, 
   }
 }
 
+// Waves claim chunks of a segment's constraints from an LDS counter (one chunk
+// = the constraints one wave covers: 64 / (G T)), so heavy and light items
+// spread over the waves as they finish; segments are ordered heaviest first.
 template <int KIND, int KMAX, class AT>
 __device__ __forceinline__ void run_segment(const ProblemDev& P, const Segment& S, const float* xs, AT* gs,
-                                            float& facc, float gsc, int tid, int nth, int logT) {
+                                            long long& facc, float gsc, float fsc, int tid, int logT, int* ctr) {
   constexpr int G = group_size(KIND, KMAX);
   constexpr int LG = Log2<G>::v;
   // keep the lane-index arithmetic inside the segment: hoisting it out of the
   // step loop for every instantiation at once exhausts the register budget
   asm volatile("" : "+v"(tid));
-  const int t = tid & ((1 << logT) - 1);
-  const int lig = (tid >> logT) & (G - 1);
-  const int slot = tid >> (logT + LG);
-  const int nslots = nth >> (logT + LG);
+  const int lane = tid & (kWave - 1);
+  const int t = lane & ((1 << logT) - 1);
+  const int lig = (lane >> logT) & (G - 1);
+  const int sub = lane >> (logT + LG);
+  const int per_wave = kWave >> (logT + LG);
   kptr<ClassRec> classes = kconst(P.classes);
   const bool uni = S.cls_fixed >= 0;
   ProdParams pp_uni{};
   if constexpr (KIND != KIND_DFT) {
     if (uni) pp_uni = prod_params(classes, S.cls_fixed);
   }
-  for (int cl = slot; cl < S.c_count; cl += nslots) {
-    const PairCtx q = pair_ctx(P, S, S.c_begin + cl);
-    if constexpr (KIND == KIND_DFT) {
-      dft_pair<KMAX, G>(P, S, cl, lig, t, logT, xs, gs, facc, gsc, q);
-    } else {
-      const ProdParams pp = uni ? pp_uni : prod_params(classes, q.cls);
-      prod_pair<KIND == KIND_PROD2 ? 2 : 1, KMAX, G>(P, S, cl, lig, t, logT, xs, gs, facc, gsc, q, pp);
+  for (;;) {
+    int base = 0;
+    if (lane == 0) base = atomicAdd(ctr, per_wave);
+    base = __builtin_amdgcn_readfirstlane(base);
+    if (base >= S.c_count) break;
+    const int cl = base + sub;
+    if (cl < S.c_count) {
+      const PairCtx q = pair_ctx(P, S, S.c_begin + cl);
+      if constexpr (KIND == KIND_DFT) {
+        dft_pair<KMAX, G>(P, S, cl, lig, t, logT, xs, gs, facc, gsc, fsc, q);
+      } else {
+        const ProdParams pp = uni ? pp_uni : prod_params(classes, q.cls);
+        prod_pair<KIND == KIND_PROD2 ? 2 : 1, KMAX, G>(P, S, cl, lig, t, logT, xs, gs, facc, gsc, fsc, q, pp);
+      }
     }
   }
 }
@@ -377,12 +401,13 @@ __device__ __forceinline__ void run_segment(const ProblemDev& P, const Segment& 
 
 #define PCLS_CASE(KIND, B, KMAX)                                     \
   case (KIND)*kNumBuckets + (B):                                     \
-    if constexpr ((B) <= MAXB) run_segment<KIND, KMAX>(P, S, xs, gs, facc, gsc, tid, nth, logT); \
+    if constexpr ((B) <= MAXB) run_segment<KIND, KMAX>(P, S, xs, gs, facc, gsc, fsc, tid, logT, ctr); \
     break;
 
 template <int MAXB, class AT>
 __device__ __forceinline__ void run_any_segment(const ProblemDev& P, const Segment& S, const float* xs, AT* gs,
-                                                float& facc, float gsc, int tid, int nth, int logT) {
+                                                long long& facc, float gsc, float fsc, int tid, int logT,
+                                                int* ctr) {
   switch (S.kind * kNumBuckets + S.bucket) {
     PCLS_BUCKET_CASES(KIND_PROD1, PCLS_CASE)
     PCLS_BUCKET_CASES(KIND_PROD2, PCLS_CASE)
@@ -403,10 +428,14 @@ struct TileArgs {
   float* g_out;      // evaluate mode: [n][ldx] or NULL
   float gsc, ginv;   // gradient fixed-point scale 2^S and 2^-S
   float fsc, finv;   // objective fixed-point scale
+  const int8_t* fixed;  // [n] or NULL: 0 free, -1 / +1 variable held at that corner value
+  float tol;            // > 0: convergence test max_v |dx| < tol per restart
+  int* iters;           // [R] or NULL: steps until convergence (n_steps if never)
 };
 
 // All n_steps steps of one tile with its state in LDS.
-// LDS: x[n][T] float | g[n][T] fixed point | F[T] 64-bit fixed point.
+// LDS: x[n][T] float | g[n][T] fixed point | F[T] 64-bit fixed point |
+//      one work counter per segment | per restart: converged flag, max |dx|.
 template <int MAXB, class AT>
 __device__ __forceinline__ void resident_tile(const ProblemDev& P, const TileArgs& A, unsigned long long* lds_raw) {
   const int logT = A.logT;
@@ -416,35 +445,49 @@ __device__ __forceinline__ void resident_tile(const ProblemDev& P, const TileArg
   AT* gs = reinterpret_cast<AT*>(reinterpret_cast<char*>(lds_raw) + ((size_t)NT * 4 + 7) / 8 * 8);
   unsigned long long* Fs =
       reinterpret_cast<unsigned long long*>(reinterpret_cast<char*>(gs) + ((size_t)NT * sizeof(AT) + 7) / 8 * 8);
+  int* ctr = reinterpret_cast<int*>(Fs + T);
+  int* conv = ctr + kMaxSegments;
+  unsigned int* dxmax = reinterpret_cast<unsigned int*>(conv + T);
   const int tid = threadIdx.x, nth = blockDim.x;
   const int r0 = A.r0, ldx = A.ldx;
   const int t = tid & (T - 1);
   const bool eval = A.obj_out != nullptr;
+  const int n_seg = P.n_segments;
 
   for (int i = tid; i < NT; i += nth) {
     const int v = i >> logT, tt = i & (T - 1);
-    xs[i] = A.X[(size_t)v * ldx + r0 + tt];
+    float x = A.X[(size_t)v * ldx + r0 + tt];
+    if (A.fixed && A.fixed[v] != 0) x = (float)A.fixed[v];
+    xs[i] = x;
     gs[i] = 0;
   }
-  if (tid < T) Fs[tid] = 0ull;
+  if (tid < T) {
+    Fs[tid] = 0ull;
+    conv[tid] = 0;
+    dxmax[tid] = 0u;
+  }
+  if (tid < n_seg) ctr[tid] = 0;
   __syncthreads();
+  float F_last = 0.f;  // threads tid < T: last evaluated objective of restart r0 + tid
 
   for (int s = 0; s < A.n_steps; ++s) {
-    float facc = 0.f;
+    long long facc = 0;
     kptr<Segment> segs = kconst(P.segments);
-    for (int sg = 0; sg < P.n_segments; ++sg) {
+    for (int sg = 0; sg < n_seg; ++sg) {
       const Segment S{segs[sg].kind,    segs[sg].bucket, segs[sg].c_begin,   segs[sg].c_count,
                       segs[sg].lit_base, segs[sg].k_fixed, segs[sg].cls_fixed, segs[sg].m_max};
-      run_any_segment<MAXB>(P, S, xs, gs, facc, A.gsc, tid, nth, logT);
+      run_any_segment<MAXB>(P, S, xs, gs, facc, A.gsc, A.fsc, tid, logT, ctr + sg);
     }
-    // lanes with equal (lane mod T) hold the same restart
+    // lanes with equal (lane mod T) hold the same restart; integer sums are exact
     for (int o = T; o < kWave; o <<= 1) facc += __shfl_xor(facc, o);
-    if ((tid & (kWave - 1)) < T) FixedAcc<unsigned long long>::add(&Fs[t], facc * A.fsc);
+    if ((tid & (kWave - 1)) < T) atomicAdd(&Fs[t], (unsigned long long)facc);
     __syncthreads();
+    if (tid < n_seg) ctr[tid] = 0;  // every wave has left the segment loops
     if (tid < T) {
-      const float F = FixedAcc<unsigned long long>::value(Fs[tid], A.finv) + P.f_const;
+      const float F = FixedAcc<unsigned long long>::value_exact(Fs[tid], A.finv) + P.f_const;
       Fs[tid] = 0ull;
       const int r = r0 + tid;
+      F_last = F;
       if (r < A.R) {
         if (A.trace) A.trace[(size_t)s * A.R + r] = F;
         if (eval) A.obj_out[r] = F;
@@ -454,19 +497,49 @@ __device__ __forceinline__ void resident_tile(const ProblemDev& P, const TileArg
       if (A.g_out) {
         for (int i = tid; i < NT; i += nth) {
           const int v = i >> logT, tt = i & (T - 1);
-          A.g_out[(size_t)v * ldx + r0 + tt] = FixedAcc<AT>::value(gs[i], A.ginv);
+          A.g_out[(size_t)v * ldx + r0 + tt] = FixedAcc<AT>::value(gs[i], A.ginv, P.occ[v]);
         }
       }
     } else {
       const float lr = A.lr;
+      float dmax = 0.f;  // this thread's elements all belong to restart t (nth is a multiple of T)
       for (int i = tid; i < NT; i += nth) {
-        const float xn = fmaf(-lr, FixedAcc<AT>::value(gs[i], A.ginv), xs[i]);
-        xs[i] = fminf(1.f, fmaxf(-1.f, xn));
+        const int v = i >> logT;
+        float xn = fmaf(-lr, FixedAcc<AT>::value(gs[i], A.ginv, P.occ[v]), xs[i]);
+        xn = fminf(1.f, fmaxf(-1.f, xn));
+        if (A.fixed && A.fixed[v] != 0) xn = (float)A.fixed[v];
+        dmax = fmaxf(dmax, fabsf(xn - xs[i]));
+        xs[i] = xn;
         gs[i] = 0;
+      }
+      if (A.tol > 0.f) {
+        for (int o = T; o < kWave; o <<= 1) dmax = fmaxf(dmax, __shfl_xor(dmax, o));
+        if ((tid & (kWave - 1)) < T) atomicMax(&dxmax[t], __float_as_uint(dmax));  // dmax >= 0: bits are monotone
       }
     }
     __syncthreads();
+    if (!eval && A.tol > 0.f) {
+      // convergence: a tile stops once every restart in it has converged
+      if (tid < T) {
+        const int r = r0 + tid;
+        if (!conv[tid] && __uint_as_float(dxmax[tid]) < A.tol) {
+          conv[tid] = 1;
+          if (A.iters && r < A.R) A.iters[r] = s + 1;
+        }
+        dxmax[tid] = 0u;
+      }
+      __syncthreads();
+      int all = 1;
+      for (int q = 0; q < T; ++q) all &= conv[q];
+      __syncthreads();  // flags read before the next step may change them
+      if (all) {
+        if (tid < T && A.trace && r0 + tid < A.R)
+          for (int q = s + 1; q < A.n_steps; ++q) A.trace[(size_t)q * A.R + r0 + tid] = F_last;
+        break;
+      }
+    }
   }
+  if (!eval && A.tol > 0.f && A.iters && tid < T && r0 + tid < A.R && !conv[tid]) A.iters[r0 + tid] = A.n_steps;
   if (!eval) {
     for (int i = tid; i < NT; i += nth) {
       const int v = i >> logT, tt = i & (T - 1);
@@ -525,6 +598,7 @@ __device__ __forceinline__ ProblemDev load_problem(kptr<BatchInst> bi) {
   P.lit = bi->P.lit;
   P.unit_weights = bi->P.unit_weights;
   P.max_k = bi->P.max_k;
+  P.occ = bi->P.occ;
   return P;
 }
 
@@ -558,6 +632,9 @@ __global__ void __launch_bounds__(1024) batch_kernel(const BatchInst* __restrict
     A.ginv = B->ginv;
     A.fsc = B->fsc;
     A.finv = B->finv;
+    A.fixed = nullptr;
+    A.tol = 0.f;
+    A.iters = nullptr;
     resident_tile<MAXB, AT>(P, A, lds_raw);
     __syncthreads();
   }
@@ -668,6 +745,7 @@ __global__ void extract_best_kernel(const int32_t* __restrict__ unsat, int R, in
 // ------------------------------------------------------------------ host side
 
 int32_t hip_fail(hipError_t e, const char* what) {
+  (void)hipGetLastError();  // clear the runtime's sticky error so later callers do not inherit it
   return set_error(PCLS_E_HIP, "%s: %s", what, hipGetErrorString(e));
 }
 
@@ -720,7 +798,7 @@ int32_t device_limits(DeviceLimits& out) {
 // F[T] 64-bit, each region 8-byte aligned.
 size_t tile_lds_bytes(int n, int T, int acc_bytes) {
   const size_t nt = (size_t)n * T;
-  return (nt * 4 + 7) / 8 * 8 + (nt * acc_bytes + 7) / 8 * 8 + (size_t)T * 8;
+  return (nt * 4 + 7) / 8 * 8 + (nt * acc_bytes + 7) / 8 * 8 + (size_t)T * 8 + 4 * kMaxSegments + (size_t)T * 8;
 }
 
 struct Launch {
@@ -783,12 +861,12 @@ int32_t check_bound(const pcls_problem* p) {
 }
 
 int32_t launch_tile(const pcls_problem* p, int R, float* d_x, float lr, int n_steps, float* trace, float* obj,
-                    float* grad, hipStream_t stream) {
+                    float* grad, hipStream_t stream, const pcls_step_options* opt = nullptr) {
   Launch L;
   int32_t st = choose_launch(p, R, L);
   if (st != PCLS_OK) return st;
   const int R_pad = round_up64(R);
-  const int tiles = R_pad >> L.logT;
+  const int tiles = (R + (1 << L.logT) - 1) >> L.logT;  // padding-only tiles are skipped
   const int sg = L.acc64 ? p->s_g64 : p->s_g32;
   TileArgs A;
   A.X = d_x;
@@ -805,6 +883,9 @@ int32_t launch_tile(const pcls_problem* p, int R, float* d_x, float lr, int n_st
   A.ginv = std::ldexp(1.0f, -sg);
   A.fsc = std::ldexp(1.0f, p->s_f);
   A.finv = std::ldexp(1.0f, -p->s_f);
+  A.fixed = opt ? opt->d_fixed : nullptr;
+  A.tol = opt ? opt->tol : 0.f;
+  A.iters = opt ? opt->d_iters : nullptr;
   if (L.acc64) {
     auto kern = p->max_bucket <= 7 ? tile_kernel<7, unsigned long long>
                                    : (p->max_bucket <= 9 ? tile_kernel<9, unsigned long long>
@@ -988,8 +1069,9 @@ int32_t batch_attrs() {
     const void* fs[] = {(const void*)batch_kernel<7, unsigned long long>, (const void*)batch_kernel<9, unsigned long long>,
                         (const void*)batch_kernel<12, unsigned long long>, (const void*)batch_kernel<7, unsigned int>,
                         (const void*)batch_kernel<9, unsigned int>, (const void*)batch_kernel<12, unsigned int>};
+    // the kernel's static LDS word sits beside the dynamic tiles
     for (const void* f : fs)
-      PCLS_HIP(hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, lim.lds_max),
+      PCLS_HIP(hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, lim.lds_max - 256),
                "hipFuncSetAttribute");
     g_batch_attr_set[dev] = true;
   }
@@ -1067,6 +1149,7 @@ int32_t pcls_upload(pcls_problem* p, void* d_ws, size_t bytes, void* stream) {
   D.lit = (const int32_t*)(b + p->off_lit);
   D.unit_weights = p->unit_weights;
   D.max_k = p->max_k;
+  D.occ = (const int32_t*)(b + p->off_occ);
   p->d_ws = d_ws;
   p->ws_bytes = bytes;
   clear_error();
@@ -1108,6 +1191,20 @@ int32_t pcls_step(const pcls_problem* p, int32_t R, float* d_x, float lr, int32_
   if (R == 0 || n_steps == 0) return PCLS_OK;
   if (!d_x) return set_error(PCLS_E_INVALID, "d_x is NULL");
   st = launch_tile(p, R, d_x, lr, n_steps, d_obj_trace, nullptr, nullptr, (hipStream_t)stream);
+  if (st == PCLS_OK) clear_error();
+  return st;
+}
+
+int32_t pcls_step_ex(const pcls_problem* p, int32_t R, float* d_x, float lr, int32_t n_steps, float* d_obj_trace,
+                     const pcls_step_options* opt, void* stream) {
+  int32_t st = check_bound(p);
+  if (st != PCLS_OK) return st;
+  if (R < 0 || n_steps < 0) return set_error(PCLS_E_INVALID, "R and n_steps must be >= 0");
+  if (!(lr == lr)) return set_error(PCLS_E_INVALID, "lr is NaN");
+  if (opt && !(opt->tol >= 0.f)) return set_error(PCLS_E_INVALID, "tol must be >= 0");
+  if (R == 0 || n_steps == 0) return PCLS_OK;
+  if (!d_x) return set_error(PCLS_E_INVALID, "d_x is NULL");
+  st = launch_tile(p, R, d_x, lr, n_steps, d_obj_trace, nullptr, nullptr, (hipStream_t)stream, opt);
   if (st == PCLS_OK) clear_error();
   return st;
 }

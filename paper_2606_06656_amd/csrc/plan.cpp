@@ -250,6 +250,7 @@ int32_t build_plan(int32_t n, int32_t m, const int32_t* row_ptr, const int32_t* 
   // ---- fixed-point scales (see plan.h)
   {
     std::vector<double> occ((size_t)n, 0.0);
+    P->occ.assign((size_t)n, 0);
     for (int c = 0; c < m; ++c) {
       const double w = std::fabs(weight ? (double)weight[c] : 1.0);
       if (P->classes[cls_orig[c]].kind == KIND_CONST) continue;
@@ -258,6 +259,7 @@ int32_t build_plan(int32_t n, int32_t m, const int32_t* row_ptr, const int32_t* 
       for (int i = row_ptr[c]; i < row_ptr[c + 1]; ++i) {
         const int l = lit[i];
         occ[(size_t)((l > 0 ? l : -l) - 1)] += w;
+        P->occ[(size_t)((l > 0 ? l : -l) - 1)] += 1;
       }
     }
     for (double v : occ) P->maxsum_g = std::max(P->maxsum_g, v);
@@ -350,6 +352,16 @@ int32_t build_plan(int32_t n, int32_t m, const int32_t* row_ptr, const int32_t* 
     j = e;
   }
 
+  // ---- heaviest segments first (work per constraint), so that the light items
+  // claimed last fill the gaps between waves
+  std::stable_sort(P->segments.begin(), P->segments.end(), [](const Segment& a, const Segment& b) {
+    auto cost = [](const Segment& s) {
+      const int k = kBucketKmax[s.bucket];
+      return s.kind == KIND_DFT ? 4 * k * (s.m_max + 1) : (s.kind == KIND_PROD2 ? 2 * k : k);
+    };
+    return cost(a) > cost(b);
+  });
+
   // ---- device image layout
   size_t off = 0;
   auto place = [&](size_t bytes) {
@@ -368,6 +380,7 @@ int32_t build_plan(int32_t n, int32_t m, const int32_t* row_ptr, const int32_t* 
   P->off_cw = place(sizeof(float) * (size_t)m);
   P->off_rowptr = place(sizeof(int32_t) * ((size_t)m + 1));
   P->off_lit = place(sizeof(int32_t) * (size_t)L);
+  P->off_occ = place(sizeof(int32_t) * (size_t)n);
   size_t total = align_up(std::max<size_t>(off, 256), 256);
   P->image.assign(total, 0);
   auto put = [&](size_t at, const void* src, size_t bytes) {
@@ -383,6 +396,7 @@ int32_t build_plan(int32_t n, int32_t m, const int32_t* row_ptr, const int32_t* 
   put(P->off_cw, P->c_w.data(), sizeof(float) * (size_t)m);
   put(P->off_rowptr, P->row_ptr.data(), sizeof(int32_t) * ((size_t)m + 1));
   put(P->off_lit, P->lit.data(), sizeof(int32_t) * (size_t)L);
+  put(P->off_occ, P->occ.data(), sizeof(int32_t) * (size_t)n);
 
   *out = P;
   *workspace_bytes = total;

@@ -23,6 +23,7 @@ struct pcls_problem {
   std::vector<float> c_w;
   std::vector<int32_t> row_ptr, lit;   // planned order
   std::vector<int32_t> perm;           // planned index -> original constraint index
+  std::vector<int32_t> occ;            // per variable: occurrences in non-constant constraints
   int32_t max_group = 1;               // largest lane group G over the segments
   int32_t max_bucket = -1;             // largest length bucket over the segments
   float f_const = 0.f;
@@ -38,7 +39,7 @@ struct pcls_problem {
   // device image
   std::vector<uint8_t> image;
   size_t off_segments = 0, off_classes = 0, off_nodes = 0, off_sp = 0, off_litT = 0, off_ck = 0,
-         off_ccls = 0, off_cw = 0, off_rowptr = 0, off_lit = 0;
+         off_ccls = 0, off_cw = 0, off_rowptr = 0, off_lit = 0, off_occ = 0;
   void* d_ws = nullptr;
   size_t ws_bytes = 0;
   pcls::ProblemDev dev{};

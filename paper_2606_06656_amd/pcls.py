@@ -22,7 +22,7 @@ STATUS_NAMES = {0: "PCLS_OK", 1: "PCLS_E_INVALID", 2: "PCLS_E_UNSUPPORTED", 3: "
 
 # exported entry points (checked by the CPU test suite against include/pcls.h)
 EXPORTS = ["pcls_plan", "pcls_plan_ex", "pcls_problem_info", "pcls_upload", "pcls_init_restarts",
-           "pcls_evaluate", "pcls_step", "pcls_extract", "pcls_set_launch", "pcls_launch_info",
+           "pcls_evaluate", "pcls_step", "pcls_step_ex", "pcls_extract", "pcls_set_launch", "pcls_launch_info",
            "pcls_destroy", "pcls_last_error",
            "pcls_batch_create", "pcls_batch_bind", "pcls_batch_set_config", "pcls_batch_get_config",
            "pcls_batch_step", "pcls_batch_capture", "pcls_batch_replay", "pcls_batch_autotune",
@@ -38,6 +38,11 @@ class PclsError(RuntimeError):
 class PlanOptions(ctypes.Structure):
     _fields_ = [("force_generic", ctypes.c_int32), ("accumulator_bits", ctypes.c_int32),
                 ("reserved", ctypes.c_int32 * 6)]
+
+
+class StepOptions(ctypes.Structure):
+    _fields_ = [("d_fixed", ctypes.c_void_p), ("tol", ctypes.c_float), ("d_iters", ctypes.c_void_p),
+                ("reserved", ctypes.c_int32 * 4)]
 
 
 class Info(ctypes.Structure):
@@ -77,6 +82,8 @@ def load_library():
     L.pcls_evaluate.argtypes = [P, i32, vp, vp, vp, vp]
     L.pcls_step.restype = i32
     L.pcls_step.argtypes = [P, i32, vp, ctypes.c_float, i32, vp, vp]
+    L.pcls_step_ex.restype = i32
+    L.pcls_step_ex.argtypes = [P, i32, vp, ctypes.c_float, i32, vp, ctypes.POINTER(StepOptions), vp]
     L.pcls_extract.restype = i32
     L.pcls_extract.argtypes = [P, i32, vp, vp, vp, vp, vp]
     L.pcls_set_launch.restype = i32
@@ -242,6 +249,23 @@ class Problem(Plan):
         check(load_library().pcls_step(self.handle, int(R), _tptr(X), float(lr), int(n_steps), _tptr(tr),
                                        _stream()))
         return tr
+
+    def step_ex(self, X, R: int, lr: float, n_steps: int, trace: bool = False, fixed=None, tol: float = 0.0,
+                want_iters: bool = False):
+        """pcls_step_ex: fixed = int8 [n] device tensor (0 free, -1 True, +1 False) or None;
+        tol > 0 enables per-restart convergence (returns iters [R] when want_iters)."""
+        import torch
+        self._check_state(X, R)
+        tr = torch.empty((n_steps, R), dtype=torch.float32, device=self.device) if trace else None
+        it = torch.empty(R, dtype=torch.int32, device=self.device) if want_iters else None
+        if fixed is not None:
+            if fixed.dtype != torch.int8 or fixed.numel() != self.n or fixed.device != self.device:
+                raise PclsError(PCLS_E_INVALID, "fixed must be an int8 tensor of n entries on the problem's device")
+        opt = StepOptions(None if fixed is None else fixed.data_ptr(), float(tol),
+                          None if it is None else it.data_ptr())
+        check(load_library().pcls_step_ex(self.handle, int(R), _tptr(X), float(lr), int(n_steps), _tptr(tr),
+                                          ctypes.byref(opt), _stream()))
+        return tr, it
 
     def extract(self, X, R: int, want_assign: bool = True):
         import torch
