@@ -257,7 +257,6 @@ def main():
     alg_bytes = algorithmic_bytes_per_step(inst.n, inst.m, inst.L, R) * args.steps
     achieved = alg_bytes / t / 1e9
     traffic = measured_traffic(key, args.steps)
-    info = prob.info()
     out = {
         "metric": METRIC,
         "value": value,
@@ -272,7 +271,7 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": key, "n": inst.n, "m": inst.m, "L": inst.L, "restarts": R, "lr": lr,
-                   "tile_restarts": info.tile_restarts, "block_threads": info.block_threads},
+                   "launch": prob.launch_info(R)},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": "tile_kernel", "launch_ms": ms,

@@ -67,8 +67,11 @@ enum {
 typedef struct pcls_plan_options {
   int32_t force_generic;    /* 1: evaluate every constraint through the K-node DFT path
                                (no one- or two-node product forms); for testing */
-  int32_t accumulator_bits; /* gradient accumulator: 0 = automatic (64-bit fixed point when
-                               the state fits on chip, else 32-bit), 32 or 64 */
+  int32_t accumulator_bits; /* gradient accumulator: 0 = automatic, 32 or 64.  Automatic
+                               takes 32-bit fixed point when its quantum is at most 2^-24
+                               (grad_scale_log2_32 >= 24: no coarser than FP32 rounding at
+                               unit scale), else 64-bit when the state fits on chip, else
+                               32-bit */
   int32_t reserved[6];
 } pcls_plan_options;
 
@@ -215,7 +218,10 @@ typedef struct pcls_batch_config {
   int32_t block_threads;    /* 256, 512 or 1024 (0 = 1024) */
   int32_t lds_budget;       /* LDS bytes per workgroup the tiles are sized for (0 = device max) */
   int32_t wgs_per_cu;       /* cap on persistent workgroups per CU (0 = as many as fit); reports the value used */
-  int32_t accumulator_bits; /* 0 = automatic, 32 or 64; reports the width used */
+  int32_t accumulator_bits; /* 0 = automatic, 32 or 64; reports the width used.  One width
+                               serves the whole batch: automatic takes 64 bits if any
+                               instance asks for them or needs them by the rule of
+                               pcls_plan_options and every instance fits with them */
 } pcls_batch_config;
 
 /*

@@ -165,17 +165,33 @@ __device__ __forceinline__ cf grp_suffix_c(cf v, int lig, int T) {
 // ------------------------------------------------------ one constraint, one restart
 // Literal i of the pair's constraint is handled by group lane i / J, slot i % J.
 
-struct PairCtx {
-  int k, cls;
+// What a lane needs from memory for its pair: the literal codes of its J
+// slots (-1 past the constraint's end or past the segment), the class and the
+// weight.  Fetching is split from computing so that the next pair's loads are
+// in flight while the current pair is evaluated.
+template <int J>
+struct Fetched {
+  int code[J];
+  int cls;
   float w;
 };
 
-__device__ __forceinline__ PairCtx pair_ctx(const ProblemDev& P, const Segment& S, int c) {
-  PairCtx q;
-  q.k = S.k_fixed > 0 ? S.k_fixed : P.c_k[c];
-  q.cls = S.cls_fixed >= 0 ? S.cls_fixed : P.c_cls[c];
-  q.w = P.unit_weights ? 1.f : P.c_w[c];
-  return q;
+template <int J>
+__device__ __forceinline__ void fetch_pair(const ProblemDev& P, const Segment& S, int c_local, int lig,
+                                           Fetched<J>& f) {
+  if (c_local >= S.c_count) {
+#pragma unroll
+    for (int j = 0; j < J; ++j) f.code[j] = -1;
+    f.cls = S.cls_fixed >= 0 ? S.cls_fixed : 0;
+    f.w = 0.f;
+    return;
+  }
+  const int32_t* lp = P.litT + S.lit_base + c_local;
+#pragma unroll
+  for (int j = 0; j < J; ++j) f.code[j] = lp[(lig * J + j) * S.c_count];
+  const int c = S.c_begin + c_local;
+  f.cls = S.cls_fixed >= 0 ? S.cls_fixed : P.c_cls[c];
+  f.w = P.unit_weights ? 1.f : P.c_w[c];
 }
 
 // Product kinds: FE - c0 = c1 prod (a + b y) [+ c2 prod (1 - y)/2];
@@ -189,25 +205,22 @@ __device__ __forceinline__ ProdParams prod_params(kptr<ClassRec> classes, int cl
 }
 
 template <int NN, int KMAX, int G, class AT>
-__device__ __forceinline__ void prod_pair(const ProblemDev& P, const Segment& S, int c_local, int lig, int t,
-                                          int logT, const float* xs, AT* gs, long long& facc, float gsc,
-                                          float fsc, const PairCtx& q, const ProdParams& pp) {
+__device__ __forceinline__ void prod_pair(const Fetched<KMAX / G>& fp, int lig, int t, int logT, const float* xs, AT* gs,
+                                          long long& facc, float gsc, float fsc, const ProdParams& pp) {
   constexpr int J = KMAX / G;
   constexpr bool kExact = KMAX <= 8;  // buckets up to 8 hold a single length
   const int T = 1 << logT;
   const float a1 = pp.a, b1 = pp.b, c1 = pp.c1, c2 = pp.c2;
-  const int32_t* lp = P.litT + S.lit_base + c_local;
 
   int addr[J];
   float f1[J], f2[J];
 #pragma unroll
   for (int j = 0; j < J; ++j) {
-    const int i = lig * J + j;
+    const int code = fp.code[j];
     addr[j] = -1;
     f1[j] = 1.f;
     f2[j] = 1.f;
-    if (kExact || i < q.k) {
-      const int code = lp[i * S.c_count];
+    if (kExact || code >= 0) {
       const int a = ((code >> 1) << logT) + t;
       const float x = xs[a];
       const float y = (code & 1) ? -x : x;
@@ -236,10 +249,10 @@ __device__ __forceinline__ void prod_pair(const ProblemDev& P, const Segment& S,
   if (lig == 0) {
     float fe = c1 * (run1 * xq1);
     if constexpr (NN == 2) fe = fmaf(c2, run2 * xq2, fe);
-    facc += fixed_term(q.w * fsc * fe);
+    facc += fixed_term(fp.w * fsc * fe);
   }
-  const float s1 = c1 * b1 * (q.w * gsc) * xp1;
-  const float s2 = -0.5f * c2 * (q.w * gsc) * xp2;
+  const float s1 = c1 * b1 * (fp.w * gsc) * xp1;
+  const float s2 = -0.5f * c2 * (fp.w * gsc) * xp2;
   float suf1 = xq1, suf2 = xq2;
 #pragma unroll
   for (int j = J - 1; j >= 0; --j) {
@@ -256,29 +269,26 @@ __device__ __forceinline__ void prod_pair(const ProblemDev& P, const Segment& S,
 // Generic kind: FE - chat_0 = sum_{m=1}^{M} Re(2 chat_m Q_m) [+ chat_{K/2} prod y];
 // dFE/dy_i = sum_m Re(2 chat_m beta_m prod_{j != i}(alpha_m + beta_m y_j)) [+ chat_{K/2} prod_{j != i} y_j].
 template <int KMAX, int G, class AT>
-__device__ __forceinline__ void dft_pair(const ProblemDev& P, const Segment& S, int c_local, int lig, int t,
-                                         int logT, const float* xs, AT* gs, long long& facc, float gsc,
-                                         float fsc, const PairCtx& q) {
+__device__ __forceinline__ void dft_pair(const ProblemDev& P, const Segment& S, const Fetched<KMAX / G>& fp, int lig, int t,
+                                         int logT, const float* xs, AT* gs, long long& facc, float gsc, float fsc) {
   constexpr int J = KMAX / G;
-  constexpr bool kExact = KMAX <= 8;
+  constexpr bool kExact = KMAX <= 8;  // buckets up to 8 hold a single length
   const int T = 1 << logT;
   kptr<ClassRec> classes = kconst(P.classes);
-  const int nyquist = classes[q.cls].nyquist;
-  const float cn = classes[q.cls].c1;
-  const int node_off = classes[q.cls].node_off;
-  const int nn = classes[q.cls].n_nodes;
-  const int32_t* lp = P.litT + S.lit_base + c_local;
+  const int nyquist = classes[fp.cls].nyquist;
+  const float cn = classes[fp.cls].c1;
+  const int node_off = classes[fp.cls].node_off;
+  const int nn = classes[fp.cls].n_nodes;
 
   int addr[J];
   float y[J], g[J];
 #pragma unroll
   for (int j = 0; j < J; ++j) {
-    const int i = lig * J + j;
+    const int code = fp.code[j];
     addr[j] = -1;
     y[j] = 1.f;
     g[j] = 0.f;
-    if (kExact || i < q.k) {
-      const int code = lp[i * S.c_count];
+    if (kExact || code >= 0) {
       const int a = ((code >> 1) << logT) + t;
       const float x = xs[a];
       y[j] = (code & 1) ? -x : x;
@@ -334,11 +344,11 @@ __device__ __forceinline__ void dft_pair(const ProblemDev& P, const Segment& S, 
       }
     }
   }
-  if (lig == 0) facc += fixed_term(q.w * fsc * fe);
+  if (lig == 0) facc += fixed_term(fp.w * fsc * fe);
 #pragma unroll
   for (int j = 0; j < J; ++j) {
     if (addr[j] >= 0) {
-      const float gv = (q.w * gsc) * g[j];
+      const float gv = (fp.w * gsc) * g[j];
       FixedAcc<AT>::add(&gs[addr[j] >> 1], (addr[j] & 1) ? -gv : gv);
     }
   }
@@ -366,21 +376,32 @@ __device__ __forceinline__ void run_segment(const ProblemDev& P, const Segment& 
   if constexpr (KIND != KIND_DFT) {
     if (uni) pp_uni = prod_params(classes, S.cls_fixed);
   }
-  for (;;) {
-    int base = 0;
-    if (lane == 0) base = atomicAdd(ctr, per_wave);
-    base = __builtin_amdgcn_readfirstlane(base);
-    if (base >= S.c_count) break;
-    const int cl = base + sub;
-    if (cl < S.c_count) {
-      const PairCtx q = pair_ctx(P, S, S.c_begin + cl);
+  constexpr int J = KMAX / G;
+  // Software pipeline: the next chunk is claimed and its literal codes are
+  // loaded before the current chunk is evaluated, so the load latency overlaps
+  // the LDS and ALU work of the current chunk.
+  auto claim = [&]() {
+    int b = 0;
+    if (lane == 0) b = atomicAdd(ctr, per_wave);
+    return __builtin_amdgcn_readfirstlane(b);
+  };
+  int base = claim();
+  Fetched<J> cur;
+  fetch_pair<J>(P, S, base + sub, lig, cur);
+  while (base < S.c_count) {
+    const int nbase = claim();
+    Fetched<J> nxt;
+    fetch_pair<J>(P, S, nbase + sub, lig, nxt);
+    if (base + sub < S.c_count) {
       if constexpr (KIND == KIND_DFT) {
-        dft_pair<KMAX, G>(P, S, cl, lig, t, logT, xs, gs, facc, gsc, fsc, q);
+        dft_pair<KMAX, G>(P, S, cur, lig, t, logT, xs, gs, facc, gsc, fsc);
       } else {
-        const ProdParams pp = uni ? pp_uni : prod_params(classes, q.cls);
-        prod_pair<KIND == KIND_PROD2 ? 2 : 1, KMAX, G>(P, S, cl, lig, t, logT, xs, gs, facc, gsc, fsc, q, pp);
+        const ProdParams pp = uni ? pp_uni : prod_params(classes, cur.cls);
+        prod_pair<KIND == KIND_PROD2 ? 2 : 1, KMAX, G>(cur, lig, t, logT, xs, gs, facc, gsc, fsc, pp);
       }
     }
+    cur = nxt;
+    base = nbase;
   }
 }
 
@@ -812,6 +833,19 @@ struct Launch {
 // most 64 / G_max (a lane group must stay inside one wave), and small enough
 // to give every compute unit at least two tiles when R allows it.  The 64-bit
 // gradient accumulator is used whenever its tile fits, else the 32-bit one.
+// Automatic accumulator width.  A 32-bit accumulator whose quantum is at most
+// 2^-24 (the FP32 unit roundoff at 1) adds no more error per term than the FP32
+// arithmetic that produced the term, and halves the LDS atomic traffic and the
+// state footprint; otherwise 64 bits are used wherever the state fits.
+constexpr int kAcc32MinScale = 24;
+
+bool auto_acc64(const pcls_problem* p, size_t cap) {
+  if (p->acc_bits == 64) return true;
+  if (p->acc_bits == 32) return false;
+  if (p->s_g32 >= kAcc32MinScale) return false;
+  return tile_lds_bytes(p->n, std::max(1, p->tile_restarts), 8) <= cap;
+}
+
 int32_t choose_launch(const pcls_problem* p, int R, Launch& L) {
   DeviceLimits lim;
   int32_t st = device_limits(lim);
@@ -819,8 +853,7 @@ int32_t choose_launch(const pcls_problem* p, int R, Launch& L) {
   const int R_pad = round_up64(R);
   const int tmax_group = kWave / std::max(1, p->max_group);
   const size_t cap = (size_t)lim.lds_max;
-  bool acc64 = p->acc_bits != 32;
-  if (p->acc_bits == 0 && tile_lds_bytes(p->n, std::max(1, p->tile_restarts), 8) > cap) acc64 = false;
+  const bool acc64 = auto_acc64(p, cap);
   if (!acc64 && p->s_g32 < 8)
     return set_error(PCLS_E_UNSUPPORTED, "state of %d variables does not fit on chip with a 64-bit accumulator and "
                      "weights are too large for a 32-bit one", p->n);
@@ -829,8 +862,11 @@ int32_t choose_launch(const pcls_problem* p, int R, Launch& L) {
   if (p->tile_restarts > 0) {
     T = p->tile_restarts;
   } else {
+    // the widest tile that still gives every CU a tile: more restarts per tile
+    // share each literal-code fetch and spread a wave's LDS accesses over
+    // fewer variables (fewer bank conflicts)
     T = 1;
-    const int want_tiles = 2 * std::max(1, lim.n_cu);
+    const int want_tiles = std::max(1, lim.n_cu);
     while (T * 2 <= tmax_group && tile_lds_bytes(p->n, T * 2, ab) <= cap && R_pad / (T * 2) >= want_tiles) T *= 2;
   }
   if (T < 1 || T > 64 || (T & (T - 1)))
@@ -843,7 +879,7 @@ int32_t choose_launch(const pcls_problem* p, int R, Launch& L) {
                      "state of %d variables x %d restarts needs %zu bytes of LDS (device limit %d)", p->n, T, lds,
                      lim.lds_max);
   int block = p->block_threads;
-  if (block <= 0) block = lds > cap / 2 ? 1024 : 512;
+  if (block <= 0) block = (lds > cap / 2 || R_pad / T <= lim.n_cu) ? 1024 : 512;
   if (block != 256 && block != 512 && block != 1024)
     return set_error(PCLS_E_INVALID, "block_threads %d must be 256, 512 or 1024", block);
   L.logT = 0;
@@ -956,11 +992,18 @@ int32_t batch_configure(BatchState& b, const pcls_batch_config& cfg_in, hipStrea
   if (cfg.accumulator_bits != 0 && cfg.accumulator_bits != 32 && cfg.accumulator_bits != 64)
     return set_error(PCLS_E_INVALID, "accumulator_bits must be 0, 32 or 64");
   const size_t budget = (size_t)cfg.lds_budget;
-  // accumulator: 64-bit unless some instance cannot fit one restart with it
-  bool acc64 = cfg.accumulator_bits != 32;
-  if (cfg.accumulator_bits == 0)
-    for (const pcls_problem* p : b.probs)
-      if (tile_lds_bytes(p->n, 1, 8) > budget) acc64 = false;
+  // accumulator (one width per launch): 64-bit if an instance asks for it or
+  // needs it by the automatic rule and every instance fits with it, else 32-bit
+  bool acc64 = cfg.accumulator_bits == 64;
+  if (cfg.accumulator_bits == 0) {
+    bool fits64 = true, asked64 = false, needs64 = false;
+    for (const pcls_problem* p : b.probs) {
+      if (tile_lds_bytes(p->n, 1, 8) > budget) fits64 = false;
+      if (p->acc_bits == 64) asked64 = true;
+      if (p->acc_bits == 0 && p->s_g32 < kAcc32MinScale) needs64 = true;
+    }
+    acc64 = asked64 || (needs64 && fits64);  // an instance that asked and does not fit is rejected below
+  }
   const int ab = acc64 ? 8 : 4;
   b.maxb = 0;
   b.items.clear();

@@ -339,7 +339,9 @@ int32_t build_plan(int32_t n, int32_t m, const int32_t* row_ptr, const int32_t* 
     S.c_count = e - j;
     const int kmax = kBucketKmax[b];
     S.lit_base = (int32_t)P->litT.size();
-    P->litT.resize(P->litT.size() + (size_t)kmax * S.c_count, 0);
+    // slots past a constraint's length hold -1, so kernels can load a whole
+    // column without first reading the length
+    P->litT.resize(P->litT.size() + (size_t)kmax * S.c_count, -1);
     for (int q = 0; q < S.c_count; ++q) {
       int cj = j + q;
       for (int i = 0; i < P->c_k[cj]; ++i)

@@ -34,9 +34,11 @@ def make_instances(count=10, seed=0):
     return out
 
 
-def setup(count=10, seed=0, R_list=None):
+def setup(count=10, seed=0, R_list=None, bits=64):
+    """Instances with one accumulator width, so that per-instance launches and the
+    batch (one width per launch) accumulate identically."""
     insts = make_instances(count, seed)
-    probs = [pcls.Problem.from_instance(i) for i in insts]
+    probs = [pcls.Problem.from_instance(i, accumulator_bits=bits) for i in insts]
     R_list = R_list or [int(r) for r in np.random.default_rng(seed + 1).choice([1, 33, 64, 100, 128], count)]
     states = []
     for k, (p, R) in enumerate(zip(probs, R_list)):
@@ -46,14 +48,15 @@ def setup(count=10, seed=0, R_list=None):
     return insts, probs, R_list, states
 
 
-def test_batch_equals_per_instance_bitwise():
-    insts, probs, Rs, states = setup(10, 0)
-    log(f"case batch R={Rs} n={[i.n for i in insts]}")
+@pytest.mark.parametrize("bits", [32, 64])
+def test_batch_equals_per_instance_bitwise(bits):
+    insts, probs, Rs, states = setup(10, 0, bits=bits)
+    log(f"case batch bits={bits} R={Rs} n={[i.n for i in insts]}")
     ref_states = [X.clone() for X in states]
     traces = [torch.zeros((4, R), device=X.device) for R, X in zip(Rs, states)]
     b = Batch(probs, Rs, states, traces)
     cfg = b.config()
-    assert cfg["n_items"] >= len(probs) and cfg["grid"] >= 1
+    assert cfg["n_items"] >= len(probs) and cfg["grid"] >= 1 and cfg["accumulator_bits"] == bits
     b.step(0.1, 4)
     for p, R, X in zip(probs, Rs, ref_states):
         p.step(X, R, 0.1, 4)

@@ -94,19 +94,20 @@ def test_weighted_constraints():
     assert_obj_grad(obj.cpu().numpy(), grad[:, :R].T.cpu().numpy(), ref, what="weighted", inst=inst)
 
 
-@pytest.mark.parametrize("seed", range(10))
-def test_c1_every_step(seed):
+@pytest.mark.parametrize("seed,bits", [(s, 0) for s in range(10)] + [(s, 64) for s in range(3)])
+def test_c1_every_step(seed, bits):
     """3-SAT n=50, m=213, R=64, 200 steps of lr 0.1: objective and gradient at
-    every iterate, and each step against clip(x - lr g_oracle)."""
+    every iterate, and each step against clip(x - lr g_oracle); with the automatic
+    accumulator (32-bit here) and with the 64-bit one."""
     inst = synth.c1_3sat(seed)
-    log(f"case c1 seed={seed}")
-    prob = pcls.Problem.from_instance(inst)
+    log(f"case c1 seed={seed} bits={bits}")
+    prob = pcls.Problem.from_instance(inst, accumulator_bits=bits)
     op = oracle_for(inst)
     R, lr = 64, 0.1
     X = prob.new_state(R)
     prob.init_restarts(X, R, seed)
     floor = quantum_floor(inst, prob, R)
-    assert prob.launch_info(R)["accumulator_bits"] == 64
+    assert prob.launch_info(R)["accumulator_bits"] == (bits or 32)
     for t in range(200):
         xt = rows_of(X, R)
         obj, grad = prob.evaluate(X, R)
