@@ -82,7 +82,8 @@ struct ProblemDev {
   const ClassRec* classes;
   const NodeRec* nodes;
   const int8_t* sp;              // spectra
-  const int32_t* litT;           // per segment: [KMAX][c_count] literal codes (v << 1 | neg)
+  const int32_t* litT;           // per segment: [KMAX][c_count] literal codes: variable in bits 0..30,
+                                 // bit 31 set for a negated literal, -1 for an empty slot
   const int32_t* c_k;            // per constraint length (planned order)
   const int32_t* c_cls;          // per constraint class
   const float* c_w;              // per constraint weight

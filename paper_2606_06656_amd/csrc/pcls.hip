@@ -81,8 +81,11 @@ struct FixedAcc<unsigned long long> {
 
 template <>
 struct FixedAcc<unsigned int> {
+  // round to nearest (ties up) in one instruction: v_cvt_rpi computes floor(v + 1/2)
   static __device__ __forceinline__ void add(unsigned int* p, float v) {
-    atomicAdd(p, (unsigned int)__float2int_rn(v));
+    int r;
+    asm("v_cvt_rpi_i32_f32 %0, %1" : "=v"(r) : "v"(v));
+    atomicAdd(p, (unsigned int)r);
   }
   static __device__ __forceinline__ float value(unsigned int a, float inv, int) { return (float)(int)a * inv; }
 };
@@ -186,13 +189,24 @@ __device__ __forceinline__ void fetch_pair(const ProblemDev& P, const Segment& S
     f.w = 0.f;
     return;
   }
-  const int32_t* lp = P.litT + S.lit_base + c_local;
+  // one 32-bit lane offset shared by every slot; the slot's column start is
+  // wave-uniform, so each load is a scalar base plus the same vector offset
+  const unsigned off = (unsigned)(lig * J) * (unsigned)S.c_count + (unsigned)c_local;
 #pragma unroll
-  for (int j = 0; j < J; ++j) f.code[j] = lp[(lig * J + j) * S.c_count];
+  for (int j = 0; j < J; ++j) {
+    const int32_t* col = P.litT + S.lit_base + (size_t)j * S.c_count;
+    f.code[j] = col[off];
+  }
   const int c = S.c_begin + c_local;
   f.cls = S.cls_fixed >= 0 ? S.cls_fixed : P.c_cls[c];
   f.w = P.unit_weights ? 1.f : P.c_w[c];
 }
+
+// Literal decode: LDS element of (variable, restart t) and the sign bit, which
+// is XORed onto x (y = s x) and onto the gradient term (dF/dx = s dF/dy).
+__device__ __forceinline__ int lit_elem(int code, int logT, int t) { return ((code & 0x7fffffff) << logT) | t; }
+__device__ __forceinline__ unsigned lit_sign(int code) { return (unsigned)code & 0x80000000u; }
+__device__ __forceinline__ float flip(float v, unsigned sb) { return __uint_as_float(__float_as_uint(v) ^ sb); }
 
 // Product kinds: FE - c0 = c1 prod (a + b y) [+ c2 prod (1 - y)/2];
 // dFE/dy_i = c1 b prod_{j != i} (a + b y_j) [- c2/2 prod_{j != i} (1 - y_j)/2].
@@ -212,19 +226,17 @@ __device__ __forceinline__ void prod_pair(const Fetched<KMAX / G>& fp, int lig, 
   const int T = 1 << logT;
   const float a1 = pp.a, b1 = pp.b, c1 = pp.c1, c2 = pp.c2;
 
-  int addr[J];
+  int el[J];
   float f1[J], f2[J];
 #pragma unroll
   for (int j = 0; j < J; ++j) {
     const int code = fp.code[j];
-    addr[j] = -1;
+    el[j] = 0;
     f1[j] = 1.f;
     f2[j] = 1.f;
-    if (kExact || code >= 0) {
-      const int a = ((code >> 1) << logT) + t;
-      const float x = xs[a];
-      const float y = (code & 1) ? -x : x;
-      addr[j] = (a << 1) | (code & 1);
+    if (kExact || code != -1) {
+      el[j] = lit_elem(code, logT, t);
+      const float y = flip(xs[el[j]], lit_sign(code));
       f1[j] = fmaf(b1, y, a1);
       if constexpr (NN == 2) f2[j] = fmaf(-0.5f, y, 0.5f);
     }
@@ -262,37 +274,38 @@ __device__ __forceinline__ void prod_pair(const Fetched<KMAX / G>& fp, int lig, 
       g = fmaf(s2 * pre2[j], suf2, g);
       suf2 *= f2[j];
     }
-    if (addr[j] >= 0) FixedAcc<AT>::add(&gs[addr[j] >> 1], (addr[j] & 1) ? -g : g);
+    if (kExact || fp.code[j] != -1) FixedAcc<AT>::add(&gs[el[j]], flip(g, lit_sign(fp.code[j])));
   }
 }
 
 // Generic kind: FE - chat_0 = sum_{m=1}^{M} Re(2 chat_m Q_m) [+ chat_{K/2} prod y];
 // dFE/dy_i = sum_m Re(2 chat_m beta_m prod_{j != i}(alpha_m + beta_m y_j)) [+ chat_{K/2} prod_{j != i} y_j].
+// cls is the pair's class; when the caller passes a wave-uniform value the class
+// record and the node table are read with scalar loads.
 template <int KMAX, int G, class AT>
-__device__ __forceinline__ void dft_pair(const ProblemDev& P, const Segment& S, const Fetched<KMAX / G>& fp, int lig, int t,
-                                         int logT, const float* xs, AT* gs, long long& facc, float gsc, float fsc) {
+__device__ __forceinline__ void dft_pair(const ProblemDev& P, int m_max, int cls, const Fetched<KMAX / G>& fp,
+                                         int lig, int t, int logT, const float* xs, AT* gs, long long& facc,
+                                         float gsc, float fsc) {
   constexpr int J = KMAX / G;
   constexpr bool kExact = KMAX <= 8;  // buckets up to 8 hold a single length
   const int T = 1 << logT;
   kptr<ClassRec> classes = kconst(P.classes);
-  const int nyquist = classes[fp.cls].nyquist;
-  const float cn = classes[fp.cls].c1;
-  const int node_off = classes[fp.cls].node_off;
-  const int nn = classes[fp.cls].n_nodes;
+  const int nyquist = classes[cls].nyquist;
+  const float cn = classes[cls].c1;
+  const int node_off = classes[cls].node_off;
+  const int nn = classes[cls].n_nodes;
 
-  int addr[J];
+  int el[J];
   float y[J], g[J];
 #pragma unroll
   for (int j = 0; j < J; ++j) {
     const int code = fp.code[j];
-    addr[j] = -1;
+    el[j] = 0;
     y[j] = 1.f;
     g[j] = 0.f;
-    if (kExact || code >= 0) {
-      const int a = ((code >> 1) << logT) + t;
-      const float x = xs[a];
-      y[j] = (code & 1) ? -x : x;
-      addr[j] = (a << 1) | (code & 1);
+    if (kExact || code != -1) {
+      el[j] = lit_elem(code, logT, t);
+      y[j] = flip(xs[el[j]], lit_sign(code));
     }
   }
   float fe = 0.f;
@@ -315,7 +328,7 @@ __device__ __forceinline__ void dft_pair(const ProblemDev& P, const Segment& S, 
     }
   }
   kptr<NodeRec> nd = kconst(P.nodes) + node_off;
-  for (int mm = 0; mm < S.m_max; ++mm) {
+  for (int mm = 0; mm < m_max; ++mm) {
     if (mm < nn) {
       const NodeRec N{nd[mm].ar, nd[mm].ai, nd[mm].br, nd[mm].bi, nd[mm].wr, nd[mm].wi, nd[mm].gr, nd[mm].gi};
       cf pre[J];
@@ -323,7 +336,7 @@ __device__ __forceinline__ void dft_pair(const ProblemDev& P, const Segment& S, 
 #pragma unroll
       for (int j = 0; j < J; ++j) {
         pre[j] = run;
-        const bool ok = kExact || addr[j] >= 0;
+        const bool ok = kExact || fp.code[j] != -1;
         const cf f = ok ? cf{fmaf(N.br, y[j], N.ar), fmaf(N.bi, y[j], N.ai)} : cf{1.f, 0.f};
         run = cmul(run, f);
       }
@@ -338,7 +351,7 @@ __device__ __forceinline__ void dft_pair(const ProblemDev& P, const Segment& S, 
       for (int j = J - 1; j >= 0; --j) {
         const cf pz = cmul(pre[j], suf);
         g[j] = fmaf(gw.r, pz.r, fmaf(-gw.i, pz.i, g[j]));  // Re(gw * pz)
-        const bool ok = kExact || addr[j] >= 0;
+        const bool ok = kExact || fp.code[j] != -1;
         const cf f = ok ? cf{fmaf(N.br, y[j], N.ar), fmaf(N.bi, y[j], N.ai)} : cf{1.f, 0.f};
         suf = cmul(suf, f);
       }
@@ -347,9 +360,9 @@ __device__ __forceinline__ void dft_pair(const ProblemDev& P, const Segment& S, 
   if (lig == 0) facc += fixed_term(fp.w * fsc * fe);
 #pragma unroll
   for (int j = 0; j < J; ++j) {
-    if (addr[j] >= 0) {
+    if (kExact || fp.code[j] != -1) {
       const float gv = (fp.w * gsc) * g[j];
-      FixedAcc<AT>::add(&gs[addr[j] >> 1], (addr[j] & 1) ? -gv : gv);
+      FixedAcc<AT>::add(&gs[el[j]], flip(gv, lit_sign(fp.code[j])));
     }
   }
 }
@@ -392,11 +405,21 @@ __device__ __forceinline__ void run_segment(const ProblemDev& P, const Segment& 
     const int nbase = claim();
     Fetched<J> nxt;
     fetch_pair<J>(P, S, nbase + sub, lig, nxt);
-    if (base + sub < S.c_count) {
+    const bool valid = base + sub < S.c_count;
+    // constraints are sorted by class inside a segment, so most chunks hold one
+    // class: then its parameters are read once per wave with scalar loads
+    const int c0 = __builtin_amdgcn_readfirstlane(cur.cls);  // lane 0 always holds a valid pair
+    const bool chunk_uni = uni || !__any(valid && cur.cls != c0);
+    if (valid) {
       if constexpr (KIND == KIND_DFT) {
-        dft_pair<KMAX, G>(P, S, cur, lig, t, logT, xs, gs, facc, gsc, fsc);
+        if (chunk_uni) {
+          kptr<ClassRec> cr = kconst(P.classes);
+          dft_pair<KMAX, G>(P, cr[c0].n_nodes, c0, cur, lig, t, logT, xs, gs, facc, gsc, fsc);
+        } else {
+          dft_pair<KMAX, G>(P, S.m_max, cur.cls, cur, lig, t, logT, xs, gs, facc, gsc, fsc);
+        }
       } else {
-        const ProdParams pp = uni ? pp_uni : prod_params(classes, cur.cls);
+        const ProdParams pp = uni ? pp_uni : prod_params(classes, chunk_uni ? c0 : cur.cls);
         prod_pair<KIND == KIND_PROD2 ? 2 : 1, KMAX, G>(cur, lig, t, logT, xs, gs, facc, gsc, fsc, pp);
       }
     }

@@ -344,8 +344,12 @@ int32_t build_plan(int32_t n, int32_t m, const int32_t* row_ptr, const int32_t* 
     P->litT.resize(P->litT.size() + (size_t)kmax * S.c_count, -1);
     for (int q = 0; q < S.c_count; ++q) {
       int cj = j + q;
-      for (int i = 0; i < P->c_k[cj]; ++i)
-        P->litT[(size_t)S.lit_base + (size_t)i * S.c_count + q] = P->lit[P->row_ptr[cj] + i];
+      for (int i = 0; i < P->c_k[cj]; ++i) {
+        // kernel code: variable in the low bits, sign in bit 31 (flipped onto x and
+        // onto the gradient term with one XOR each)
+        const uint32_t code = (uint32_t)P->lit[P->row_ptr[cj] + i];
+        P->litT[(size_t)S.lit_base + (size_t)i * S.c_count + q] = (int32_t)((code >> 1) | ((code & 1u) << 31));
+      }
     }
     const int G = group_size(S.kind, kmax);
     P->max_group = std::max(P->max_group, G);
