@@ -20,6 +20,9 @@ ARCH = os.environ.get("PCLS_OFFLOAD_ARCH", "gfx950")
 HIP_FLAGS = [
     "-O3", "-std=c++17", "-fPIC", "-shared", f"--offload-arch={ARCH}",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # work claims are single-lane atomics on one LDS word: the pass that turns
+    # uniform-address atomics into a wave reduction only adds instructions there
+    "-mllvm", "-amdgpu-atomic-optimizer-strategy=None",
     "-Wall", "-Wno-unused-function",
 ]
 

@@ -370,11 +370,28 @@ __device__ __forceinline__ void dft_pair(const ProblemDev& P, int m_max, int cls
 // Waves claim chunks of a segment's constraints from an LDS counter (one chunk
 // = the constraints one wave covers: 64 / (G T)), so heavy and light items
 // spread over the waves as they finish; segments are ordered heaviest first.
-template <int KIND, int KMAX, class AT>
+// Pairs each lane takes per claim: short product constraints are cheap, so a
+// lane takes several of them per claim, which amortises the claim, the fetch
+// addressing and the loop control over more literals.
+// Kernels built for long constraints (MAXB above the 8-literal bucket) keep one
+// pair per lane: their register budget goes to the long groups.
+template <int KIND, int J, int MAXB>
+constexpr int pairs_per_lane() {
+  return (KIND == KIND_DFT || MAXB > 7) ? 1 : (J <= 4 ? 4 : (J <= 8 ? 2 : 1));
+}
+
+template <int J, int U>
+struct FetchedU {
+  Fetched<J> p[U];
+};
+
+template <int KIND, int KMAX, int MAXB, class AT>
 __device__ __forceinline__ void run_segment(const ProblemDev& P, const Segment& S, const float* xs, AT* gs,
                                             long long& facc, float gsc, float fsc, int tid, int logT, int* ctr) {
   constexpr int G = group_size(KIND, KMAX);
   constexpr int LG = Log2<G>::v;
+  constexpr int J = KMAX / G;
+  constexpr int U = pairs_per_lane<KIND, J, MAXB>();
   // keep the lane-index arithmetic inside the segment: hoisting it out of the
   // step loop for every instantiation at once exhausts the register budget
   asm volatile("" : "+v"(tid));
@@ -382,45 +399,54 @@ __device__ __forceinline__ void run_segment(const ProblemDev& P, const Segment& 
   const int t = lane & ((1 << logT) - 1);
   const int lig = (lane >> logT) & (G - 1);
   const int sub = lane >> (logT + LG);
-  const int per_wave = kWave >> (logT + LG);
+  const int per_wave = kWave >> (logT + LG);  // pairs one wave covers side by side
   kptr<ClassRec> classes = kconst(P.classes);
   const bool uni = S.cls_fixed >= 0;
   ProdParams pp_uni{};
   if constexpr (KIND != KIND_DFT) {
     if (uni) pp_uni = prod_params(classes, S.cls_fixed);
   }
-  constexpr int J = KMAX / G;
-  // Software pipeline: the next chunk is claimed and its literal codes are
-  // loaded before the current chunk is evaluated, so the load latency overlaps
-  // the LDS and ALU work of the current chunk.
+  // Software pipeline: the next chunk of U * per_wave constraints is claimed
+  // and its literal codes are loaded before the current chunk is evaluated, so
+  // the load latency overlaps the LDS and ALU work of the current chunk.
   auto claim = [&]() {
     int b = 0;
-    if (lane == 0) b = atomicAdd(ctr, per_wave);
+    if (lane == 0) b = atomicAdd(ctr, U * per_wave);
     return __builtin_amdgcn_readfirstlane(b);
   };
+  auto fetch = [&](int b, FetchedU<J, U>& f) {
+#pragma unroll
+    for (int u = 0; u < U; ++u) fetch_pair<J>(P, S, b + u * per_wave + sub, lig, f.p[u]);
+  };
   int base = claim();
-  Fetched<J> cur;
-  fetch_pair<J>(P, S, base + sub, lig, cur);
+  FetchedU<J, U> cur;
+  fetch(base, cur);
   while (base < S.c_count) {
     const int nbase = claim();
-    Fetched<J> nxt;
-    fetch_pair<J>(P, S, nbase + sub, lig, nxt);
-    const bool valid = base + sub < S.c_count;
-    // constraints are sorted by class inside a segment, so most chunks hold one
-    // class: then its parameters are read once per wave with scalar loads
-    const int c0 = __builtin_amdgcn_readfirstlane(cur.cls);  // lane 0 always holds a valid pair
-    const bool chunk_uni = uni || !__any(valid && cur.cls != c0);
-    if (valid) {
-      if constexpr (KIND == KIND_DFT) {
-        if (chunk_uni) {
-          kptr<ClassRec> cr = kconst(P.classes);
-          dft_pair<KMAX, G>(P, cr[c0].n_nodes, c0, cur, lig, t, logT, xs, gs, facc, gsc, fsc);
+    FetchedU<J, U> nxt;
+    fetch(nbase, nxt);
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int b_u = base + u * per_wave;
+      if (u > 0 && b_u >= S.c_count) break;  // wave-uniform: the rest of the chunk is past the segment
+      const Fetched<J>& fp = cur.p[u];
+      const bool valid = b_u + sub < S.c_count;
+      // constraints are sorted by class inside a segment, so most chunks hold
+      // one class: then its parameters are read once per wave with scalar loads
+      const int c0 = __builtin_amdgcn_readfirstlane(fp.cls);  // lane 0 holds a valid pair
+      const bool chunk_uni = uni || !__any(valid && fp.cls != c0);
+      if (valid) {
+        if constexpr (KIND == KIND_DFT) {
+          if (chunk_uni) {
+            kptr<ClassRec> cr = kconst(P.classes);
+            dft_pair<KMAX, G>(P, cr[c0].n_nodes, c0, fp, lig, t, logT, xs, gs, facc, gsc, fsc);
+          } else {
+            dft_pair<KMAX, G>(P, S.m_max, fp.cls, fp, lig, t, logT, xs, gs, facc, gsc, fsc);
+          }
         } else {
-          dft_pair<KMAX, G>(P, S.m_max, cur.cls, cur, lig, t, logT, xs, gs, facc, gsc, fsc);
+          const ProdParams pp = uni ? pp_uni : prod_params(classes, chunk_uni ? c0 : fp.cls);
+          prod_pair<KIND == KIND_PROD2 ? 2 : 1, KMAX, G>(fp, lig, t, logT, xs, gs, facc, gsc, fsc, pp);
         }
-      } else {
-        const ProdParams pp = uni ? pp_uni : prod_params(classes, chunk_uni ? c0 : cur.cls);
-        prod_pair<KIND == KIND_PROD2 ? 2 : 1, KMAX, G>(cur, lig, t, logT, xs, gs, facc, gsc, fsc, pp);
       }
     }
     cur = nxt;
@@ -445,7 +471,7 @@ __device__ __forceinline__ void run_segment(const ProblemDev& P, const Segment& 
 
 #define PCLS_CASE(KIND, B, KMAX)                                     \
   case (KIND)*kNumBuckets + (B):                                     \
-    if constexpr ((B) <= MAXB) run_segment<KIND, KMAX>(P, S, xs, gs, facc, gsc, fsc, tid, logT, ctr); \
+    if constexpr ((B) <= MAXB) run_segment<KIND, KMAX, MAXB>(P, S, xs, gs, facc, gsc, fsc, tid, logT, ctr); \
     break;
 
 template <int MAXB, class AT>
