@@ -89,6 +89,9 @@ typedef struct pcls_info {
   int32_t block_threads;     /* threads per workgroup of the resident engine (0 = auto) */
   size_t workspace_bytes;
   size_t lds_bytes_per_restart; /* on-chip bytes one restart's state needs */
+  int32_t cons_by_kind[5];   /* constraints per evaluation path: one-node product, two-node
+                                product, K-node DFT, truncated count distribution (k <= 8,
+                                window of at most 4 counts), constant */
 } pcls_info;
 
 /*

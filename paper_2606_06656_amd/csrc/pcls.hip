@@ -370,6 +370,58 @@ __device__ __forceinline__ void dft_pair(const ProblemDev& P, int m_max, int cls
 // Waves claim chunks of a segment's constraints from an LDS counter (one chunk
 // = the constraints one wave covers: 64 / (G T)), so heavy and light items
 // spread over the waves as they finish; segments are ordered heaviest first.
+// PMF kind (k <= 8, one lane per pair).  With pi_i = 1/2 - h y_i the
+// probability that literal i adds to the count C, the truncated distribution
+// q_c = Pr[C = c], c < 4, follows q <- q (1 - pi_i) + shift(q) pi_i; the value
+// is sum_c d_c q_c.  Reverse mode: with lambda = d after the last literal,
+// dFE/dpi_i = sum_c pre_i[c] (lambda_{c+1} - lambda_c) (lambda_4 = 0) where pre_i
+// is q before literal i, then lambda_c <- lambda_c + pi_i (lambda_{c+1} - lambda_c).
+// Every update is a convex combination, so no cancellation arises.
+template <int KMAX, class AT>
+__device__ __forceinline__ void pmf_pair(const ProblemDev& P, int cls, const Fetched<KMAX>& fp, int t, int logT,
+                                         const float* xs, AT* gs, long long& facc, float gsc, float fsc) {
+  constexpr int J = KMAX;  // buckets up to 8 hold a single length
+  constexpr int W = kPmfWindow;
+  kptr<ClassRec> classes = kconst(P.classes);
+  kptr<NodeRec> nd = kconst(P.nodes) + classes[cls].node_off;
+  float d[W] = {nd[0].ar, nd[0].ai, nd[0].br, nd[0].bi};
+  const float h = nd[0].wr;
+
+  int el[J];
+  float pi[J], pre[J][W];
+  float q[W] = {1.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int j = 0; j < J; ++j) {
+    el[j] = lit_elem(fp.code[j], logT, t);
+    const float y = flip(xs[el[j]], lit_sign(fp.code[j]));
+    pi[j] = fmaf(-h, y, 0.5f);
+#pragma unroll
+    for (int c = 0; c < W; ++c) pre[j][c] = q[c];
+#pragma unroll
+    for (int c = W - 1; c >= 1; --c) q[c] = fmaf(pi[j], q[c - 1] - q[c], q[c]);
+    q[0] = fmaf(-pi[j], q[0], q[0]);
+  }
+  float fe = 0.f;
+#pragma unroll
+  for (int c = 0; c < W; ++c) fe = fmaf(d[c], q[c], fe);
+  facc += fixed_term(fp.w * fsc * fe);
+  // dFE/dy_i = -h dFE/dpi_i
+  const float coef = -h * (fp.w * gsc);
+  float* lam = d;
+#pragma unroll
+  for (int j = J - 1; j >= 0; --j) {
+    float diff[W], gp = 0.f;
+#pragma unroll
+    for (int c = 0; c < W; ++c) {
+      diff[c] = (c + 1 < W ? lam[c + 1] : 0.f) - lam[c];
+      gp = fmaf(pre[j][c], diff[c], gp);
+    }
+#pragma unroll
+    for (int c = 0; c < W; ++c) lam[c] = fmaf(pi[j], diff[c], lam[c]);
+    FixedAcc<AT>::add(&gs[el[j]], flip(coef * gp, lit_sign(fp.code[j])));
+  }
+}
+
 // Pairs each lane takes per claim: short product constraints are cheap, so a
 // lane takes several of them per claim, which amortises the claim, the fetch
 // addressing and the loop control over more literals.
@@ -377,7 +429,7 @@ __device__ __forceinline__ void dft_pair(const ProblemDev& P, int m_max, int cls
 // pair per lane: their register budget goes to the long groups.
 template <int KIND, int J, int MAXB>
 constexpr int pairs_per_lane() {
-  return (KIND == KIND_DFT || MAXB > 7) ? 1 : (J <= 4 ? 4 : (J <= 8 ? 2 : 1));
+  return (KIND == KIND_DFT || KIND == KIND_PMF || MAXB > 7) ? 1 : (J <= 4 ? 4 : (J <= 8 ? 2 : 1));
 }
 
 template <int J, int U>
@@ -403,7 +455,7 @@ __device__ __forceinline__ void run_segment(const ProblemDev& P, const Segment& 
   kptr<ClassRec> classes = kconst(P.classes);
   const bool uni = S.cls_fixed >= 0;
   ProdParams pp_uni{};
-  if constexpr (KIND != KIND_DFT) {
+  if constexpr (KIND == KIND_PROD1 || KIND == KIND_PROD2) {
     if (uni) pp_uni = prod_params(classes, S.cls_fixed);
   }
   // Software pipeline: the next chunk of U * per_wave constraints is claimed
@@ -443,6 +495,8 @@ __device__ __forceinline__ void run_segment(const ProblemDev& P, const Segment& 
           } else {
             dft_pair<KMAX, G>(P, S.m_max, fp.cls, fp, lig, t, logT, xs, gs, facc, gsc, fsc);
           }
+        } else if constexpr (KIND == KIND_PMF) {
+          pmf_pair<KMAX>(P, chunk_uni ? c0 : fp.cls, fp, t, logT, xs, gs, facc, gsc, fsc);
         } else {
           const ProdParams pp = uni ? pp_uni : prod_params(classes, chunk_uni ? c0 : fp.cls);
           prod_pair<KIND == KIND_PROD2 ? 2 : 1, KMAX, G>(fp, lig, t, logT, xs, gs, facc, gsc, fsc, pp);
@@ -469,6 +523,16 @@ __device__ __forceinline__ void run_segment(const ProblemDev& P, const Segment& 
   X(KIND, 11, 128)                 \
   X(KIND, 12, 256)
 
+#define PCLS_SHORT_BUCKET_CASES(KIND, X) \
+  X(KIND, 0, 1)                          \
+  X(KIND, 1, 2)                          \
+  X(KIND, 2, 3)                          \
+  X(KIND, 3, 4)                          \
+  X(KIND, 4, 5)                          \
+  X(KIND, 5, 6)                          \
+  X(KIND, 6, 7)                          \
+  X(KIND, 7, 8)
+
 #define PCLS_CASE(KIND, B, KMAX)                                     \
   case (KIND)*kNumBuckets + (B):                                     \
     if constexpr ((B) <= MAXB) run_segment<KIND, KMAX, MAXB>(P, S, xs, gs, facc, gsc, fsc, tid, logT, ctr); \
@@ -482,6 +546,7 @@ __device__ __forceinline__ void run_any_segment(const ProblemDev& P, const Segme
     PCLS_BUCKET_CASES(KIND_PROD1, PCLS_CASE)
     PCLS_BUCKET_CASES(KIND_PROD2, PCLS_CASE)
     PCLS_BUCKET_CASES(KIND_DFT, PCLS_CASE)
+    PCLS_SHORT_BUCKET_CASES(KIND_PMF, PCLS_CASE)
     default:
       break;
   }
@@ -1208,6 +1273,7 @@ int32_t pcls_problem_info(const pcls_problem* p, pcls_info* info) {
   info->block_threads = p->block_threads;
   info->workspace_bytes = p->image.size();
   info->lds_bytes_per_restart = (size_t)p->n * 2 * sizeof(float);
+  for (int32_t c : p->c_cls) ++info->cons_by_kind[p->classes[(size_t)c].kind];
   clear_error();
   return PCLS_OK;
 }

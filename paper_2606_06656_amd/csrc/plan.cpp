@@ -53,6 +53,8 @@ struct ClassKey {
 // Evaluation kind from the shape of the spectrum.  FE = sum_t sp_t Pr[T = t]
 // where Pr[T = 0] = prod u_i, Pr[T = k] = prod p_i (u = (1+y)/2, p = (1-y)/2)
 // and sum_t (-1)^t Pr[T = t] = prod y_i.
+static int pmf_window(const std::vector<int>& sp, float* d, float* h);
+
 static void classify(const std::vector<int>& sp, bool force_generic, ClassRec& C) {
   const int k = (int)sp.size() - 1;
   bool all_eq = true, tail_eq = true, head_eq = true, alt = true, mid_eq = true;
@@ -103,8 +105,33 @@ static void classify(const std::vector<int>& sp, bool force_generic, ClassRec& C
       C.c2 = (float)(sp[k] - sp[1]);
       return;
     }
+    if (k <= kPmfMaxK && pmf_window(sp, nullptr, nullptr) <= kPmfWindow) {
+      C.kind = KIND_PMF;
+      return;
+    }
   }
   C.kind = KIND_DFT;
+}
+
+// PMF kind: the shorter of the two windows.  Counting true literals,
+// FE = sp_k + sum_{t < w} (sp_t - sp_k) Pr[T = t] with w = 1 + the last t where
+// sp_t != sp_k; counting false ones (F = k - T), FE = sp_0 + sum_{f < w}
+// (sp_{k-f} - sp_0) Pr[F = f].  Returns w; fills d[0..3] (zero past w) and h.
+static int pmf_window(const std::vector<int>& sp, float* d, float* h) {
+  const int k = (int)sp.size() - 1;
+  int wt = 0, wf = 0;
+  for (int t = 0; t <= k; ++t)
+    if (sp[t] != sp[k]) wt = t + 1;
+  for (int f = 0; f <= k; ++f)
+    if (sp[k - f] != sp[0]) wf = f + 1;
+  const bool count_true = wt <= wf;
+  const int w = count_true ? wt : wf;
+  if (d) {
+    for (int c = 0; c < kPmfWindow; ++c)
+      d[c] = (c < w && c <= k) ? (float)(count_true ? sp[c] - sp[k] : sp[k - c] - sp[0]) : 0.f;
+    *h = count_true ? 0.5f : -0.5f;
+  }
+  return w;
 }
 
 // Inverse-DFT weights over the K = k + 1 roots of unity.  With
@@ -232,6 +259,20 @@ int32_t build_plan(int32_t n, int32_t m, const int32_t* row_ptr, const int32_t* 
       C.k = k;
       classify(sp, force_generic, C);
       if (C.kind == KIND_DFT) dft_weights(sp, C, P->nodes);
+      if (C.kind == KIND_PMF) {
+        NodeRec N{};
+        float d[kPmfWindow], h;
+        pmf_window(sp, d, &h);
+        N.ar = d[0];
+        N.ai = d[1];
+        N.br = d[2];
+        N.bi = d[3];
+        N.wr = h;
+        C.c0 = (float)(h > 0.f ? sp[k] : sp[0]);
+        C.node_off = (int32_t)P->nodes.size();
+        C.n_nodes = 1;
+        P->nodes.push_back(N);
+      }
       C.sp_off = (int32_t)P->sp.size();
       for (int t = 0; t <= k; ++t) P->sp.push_back((int8_t)sp[t]);
       int id = (int)P->classes.size();
@@ -363,7 +404,9 @@ int32_t build_plan(int32_t n, int32_t m, const int32_t* row_ptr, const int32_t* 
   std::stable_sort(P->segments.begin(), P->segments.end(), [](const Segment& a, const Segment& b) {
     auto cost = [](const Segment& s) {
       const int k = kBucketKmax[s.bucket];
-      return s.kind == KIND_DFT ? 4 * k * (s.m_max + 1) : (s.kind == KIND_PROD2 ? 2 * k : k);
+      return s.kind == KIND_DFT ? 4 * k * (s.m_max + 1)
+             : s.kind == KIND_PMF ? 6 * k
+             : (s.kind == KIND_PROD2 ? 2 * k : k);
     };
     return cost(a) > cost(b);
   });

@@ -51,7 +51,10 @@ class Info(ctypes.Structure):
                 ("accumulator_bits", ctypes.c_int32), ("grad_scale_log2_64", ctypes.c_int32),
                 ("grad_scale_log2_32", ctypes.c_int32), ("obj_scale_log2", ctypes.c_int32),
                 ("tile_restarts", ctypes.c_int32), ("block_threads", ctypes.c_int32),
-                ("workspace_bytes", ctypes.c_size_t), ("lds_bytes_per_restart", ctypes.c_size_t)]
+                ("workspace_bytes", ctypes.c_size_t), ("lds_bytes_per_restart", ctypes.c_size_t),
+                ("cons_by_kind", ctypes.c_int32 * 5)]
+
+KIND_NAMES = ("prod1", "prod2", "dft", "pmf", "const")
 
 
 _lib = None

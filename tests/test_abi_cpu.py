@@ -109,7 +109,9 @@ def test_info_and_launch_settings():
     p = pcls.Plan.from_instance(inst)
     info = p.info()
     assert (info.n_vars, info.n_cons, info.n_lits, info.max_len) == (2000, 6800, 22600, 8)
-    assert info.n_segments == 3  # OR-3 products, XOR-5 products, CARD>=3 of 8 through the DFT
+    assert info.n_segments == 3  # OR-3 products, XOR-5 products, CARD>=3 of 8 through the count window
+    assert dict(zip(pcls.KIND_NAMES, info.cons_by_kind)) == {"prod1": 6600, "prod2": 0, "dft": 0, "pmf": 200,
+                                                             "const": 0}
     assert info.lds_bytes_per_restart == 2000 * 8
     p.set_launch(4, 1024)
     assert (p.info().tile_restarts, p.info().block_threads) == (4, 1024)
@@ -121,6 +123,7 @@ def test_info_and_launch_settings():
         p.set_launch(64, 0)  # 2000 x 64 restarts do not fit in LDS
     g = pcls.Plan.from_instance(inst, force_generic=True)
     assert g.info().n_segments == 3
+    assert list(g.info().cons_by_kind) == [0, 0, 6800, 0, 0]
 
 
 def test_plan_segments_by_kind():
@@ -128,4 +131,38 @@ def test_plan_segments_by_kind():
     p = pcls.Plan.from_instance(inst)
     info = p.info()
     assert info.n_cons == inst.m and info.n_lits == inst.L
-    assert 1 <= info.n_segments <= 3 * 13
+    assert 1 <= info.n_segments <= 4 * 13
+
+
+def _expected_kind(sp):
+    """Evaluation path the planner should pick for a spectrum (sp_t = -1 when the
+    constraint holds with t true literals): a product form when one exists, the
+    count window when k <= 8 and the spectrum is constant past 4 counts at one
+    end, else the DFT."""
+    k = len(sp) - 1
+    if all(v == sp[0] for v in sp):
+        return "const"
+    if all(v == sp[1] for v in sp[1:]) or all(v == sp[0] for v in sp[:k]):
+        return "prod1"
+    if all(sp[t] == (sp[0] if t % 2 == 0 else -sp[0]) for t in range(k + 1)):
+        return "prod1"
+    if k >= 3 and all(v == sp[1] for v in sp[1:k]):
+        return "prod2"
+    wt = max([t + 1 for t in range(k + 1) if sp[t] != sp[k]], default=0)
+    wf = max([f + 1 for f in range(k + 1) if sp[k - f] != sp[0]], default=0)
+    if k <= 8 and min(wt, wf) <= 4:
+        return "pmf"
+    return "dft"
+
+
+@pytest.mark.parametrize("k", range(1, 13))
+def test_plan_picks_evaluation_path(k):
+    from oracle import coeffs as C
+    for ctype in (C.OR, C.XOR, C.CARD_GE, C.NAE, C.EO, C.AMO, C.EK):
+        params = range(k + 1) if ctype in (C.CARD_GE, C.EK) else ([0, 1] if ctype == C.XOR else [0])
+        for prm in params:
+            inst = synth.Instance(n=k, row_ptr=np.array([0, k], np.int32), lit=np.arange(1, k + 1, dtype=np.int32),
+                                  ctype=np.array([ctype], np.int8), param=np.array([prm], np.int32))
+            counts = dict(zip(pcls.KIND_NAMES, pcls.Plan.from_instance(inst).info().cons_by_kind))
+            want = _expected_kind(list(C.spectrum(ctype, k, prm)))
+            assert counts[want] == 1, (C.TYPE_NAMES[ctype], k, prm, counts, want)
