@@ -62,18 +62,45 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic(workload_key: str, steps: int):
-    """HBM bytes per launch from committed rocprofv3 counter runs, if they were
-    taken on the current kernel source; else None."""
-    path = os.path.join(PROFILE_DIR, f"tile_kernel_{workload_key}_traffic.json")
+# Instruction-issue roof of the vector ALUs: 256 CUs x 4 SIMDs, one wave64
+# instruction per SIMD every 4 cycles, 2.4 GHz.
+VALU_PEAK_GINST = 256 * 4 * 2.4 / 4
+
+
+def profile_record(kernel: str, workload_key: str, kind: str, steps_per_launch: int):
+    """Per-launch figures ("traffic": HBM bytes from the FETCH_SIZE / WRITE_SIZE
+    passes scaled by the copy calibration; "counters": SQ instruction counts)
+    from a committed rocprofv3 run, if it was taken on the current kernel source
+    with the same launch size; else None."""
+    path = os.path.join(PROFILE_DIR, f"{kernel}_{workload_key}_{kind}.json")
     if not os.path.exists(path):
         return None
     with open(path) as f:
         rec = json.load(f)
-    if rec.get("source_sha") != kernel_source_hash():
+    if rec.get("source_sha") != kernel_source_hash() or rec.get("steps_per_launch") != steps_per_launch:
         return None
-    per_step = rec.get("hbm_bytes_per_step")
-    return None if per_step is None else float(per_step) * steps
+    return rec
+
+
+def roofline(kernel: str, key: str, alg_bytes_per_launch: float, launch_ms: float, steps_per_launch: int):
+    """Gather-model HBM roofline of the dominant kernel (algorithmic bytes per
+    launch over the average launch time), with the measured HBM traffic and the
+    binding on-chip resource when committed profiles of this kernel exist."""
+    achieved = alg_bytes_per_launch / (launch_ms / 1e3) / 1e9
+    tr = profile_record(kernel, key, "traffic", steps_per_launch)
+    out = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+           "frac": achieved / HBM_PEAK_GBS, "traffic": None if tr is None else tr["hbm_bytes_per_launch"],
+           "kernel": kernel, "launch_ms": launch_ms, "steps_per_launch": steps_per_launch,
+           "model": "gather model: 8 B per literal-eval + 8 B per (variable, restart) + CSR per step"}
+    ct = profile_record(kernel, key, "counters", steps_per_launch)
+    if ct is not None:
+        from paper_2606_06656_amd import pcls
+        rate = ct["valu_insts_per_launch"] / (launch_ms / 1e3) / 1e9
+        out["binding"] = {"bound": "alu", "resource": "VALU instruction issue", "achieved": rate,
+                          "peak": VALU_PEAK_GINST, "peak_measured": pcls.valu_issue_rate() / 1e9,
+                          "unit": "G wave64-instr/s", "frac": rate / VALU_PEAK_GINST,
+                          "valu_insts_per_launch": ct["valu_insts_per_launch"]}
+    return out
 
 
 def cpu_baseline(inst, lr: float, budget_s: float = 12.0, R_sample: int = 16):
@@ -116,7 +143,7 @@ def bench_batch(args, insts, R, lr, key):
         p.init_restarts(X, R, 4000 + k)
         states.append(X)
     b = Batch(probs, [R] * len(probs), states)
-    tune = b.autotune(lr, probe_steps=3)
+    tune = b.autotune(lr, probe_steps=3, cache_path=args.tune_cache)
     S = args.graph_steps
     reps = max(1, args.steps // S)
     steps = reps * S
@@ -147,7 +174,6 @@ def bench_batch(args, insts, R, lr, key):
     ms_b = e0.elapsed_time(e1)
     base_rate = R * L_tot * bs / (ms_b / 1e3)
     alg = sum(algorithmic_bytes_per_step(i.n, i.m, i.L, R) for i in insts) * S
-    achieved = alg / (ms / reps / 1e3) / 1e9
     cfg = b.config()
     out = {
         "metric": METRIC, "value": value, "unit": "literal-evals/s", "n_gpus": 1, "steps": steps,
@@ -158,10 +184,7 @@ def bench_batch(args, insts, R, lr, key):
         "per_instance_launches": {"value": base_rate, "unit": "literal-evals/s", "steps": bs,
                                   "ms_per_step": ms_b / bs, "launches_per_step": len(insts),
                                   "speedup_of_batched": value / base_rate},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": "batch_kernel",
-                     "launch_ms": ms / reps,
-                     "model": "gather model: 8 B per literal-eval + 8 B per (variable, restart) + CSR per step"},
+        "roofline": roofline("batch_kernel", key, alg, ms / reps, S),
     }
     print(json.dumps(out), flush=True)
 
@@ -200,7 +223,10 @@ def main():
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=100)
     ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c3long", "c4"])
+    ap.add_argument("--steps-per-launch", type=int, default=100,
+                    help="steps per launch of the resident kernel (timed and warm-up launches alike)")
     ap.add_argument("--graph-steps", type=int, default=50, help="c4: steps captured per graph replay")
+    ap.add_argument("--tune-cache", default=None, help="c4: autotuner cache file (reused when present)")
     ap.add_argument("--baseline-steps", type=int, default=10, help="c4: steps of per-instance plain launches")
     ap.add_argument("--tile", type=int, default=0, help="restarts per workgroup (0 = auto)")
     ap.add_argument("--block", type=int, default=0, help="threads per workgroup (0 = auto)")
@@ -240,31 +266,31 @@ def main():
     X = prob.new_state(R)
     prob.init_restarts(X, R, 2)
     stream = torch.cuda.current_stream()
-    if args.warmup > 0:
-        prob.step(X, R, lr, args.warmup)
+    S = max(1, min(args.steps_per_launch, args.steps))
+    n_launch = max(1, args.steps // S)
+    steps = n_launch * S
+    for _ in range((args.warmup + S - 1) // S):
+        prob.step(X, R, lr, S)
     torch.cuda.synchronize()
 
     start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     start.record(stream)
-    prob.step(X, R, lr, args.steps)  # one launch of the resident kernel runs all K steps
+    for _ in range(n_launch):
+        prob.step(X, R, lr, S)  # one launch of the resident kernel runs S steps
     end.record(stream)
     torch.cuda.synchronize()
     ms = start.elapsed_time(end)
     t = ms / 1e3
 
-    lit_evals = R * inst.L * args.steps
-    value = lit_evals / t
-    alg_bytes = algorithmic_bytes_per_step(inst.n, inst.m, inst.L, R) * args.steps
-    achieved = alg_bytes / t / 1e9
-    traffic = measured_traffic(key, args.steps)
+    value = R * inst.L * steps / t
     out = {
         "metric": METRIC,
         "value": value,
         "unit": "literal-evals/s",
         "n_gpus": 1,
-        "steps": args.steps,
+        "steps": steps,
         "warmup": args.warmup,
-        "ms_per_step": ms / args.steps,
+        "ms_per_step": ms / steps,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -272,10 +298,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": key, "n": inst.n, "m": inst.m, "L": inst.L, "restarts": R, "lr": lr,
                    "launch": prob.launch_info(R)},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "kernel": "tile_kernel", "launch_ms": ms,
-                     "model": "gather model: 8 B per literal-eval + 8 B per (variable, restart) + CSR per step"},
+        "roofline": roofline("tile_kernel", key, algorithmic_bytes_per_step(inst.n, inst.m, inst.L, R) * S,
+                             ms / n_launch, S),
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(inst, lr, args.cpu_budget)

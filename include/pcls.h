@@ -269,6 +269,16 @@ int32_t pcls_destroy(pcls_problem* p);
 /* Thread-local description of the last error; valid until the next call. */
 const char* pcls_last_error(void);
 
+/*
+ * Measurement utility (not part of the method): launches `blocks` workgroups of
+ * 256 threads, each lane running iters x 64 fused multiply-adds in eight
+ * independent chains with no memory traffic, then one store per lane to
+ * d_out[blocks * 256] (device, caller-owned).  Timing it gives the VALU
+ * instruction-issue ceiling: blocks * 4 * iters * 64 wave64 instructions.
+ * Asynchronous on `stream`; PCLS_E_INVALID for a non-positive size or NULL.
+ */
+int32_t pcls_valu_probe(int32_t blocks, int32_t iters, float* d_out, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -26,7 +26,7 @@ EXPORTS = ["pcls_plan", "pcls_plan_ex", "pcls_problem_info", "pcls_upload", "pcl
            "pcls_destroy", "pcls_last_error",
            "pcls_batch_create", "pcls_batch_bind", "pcls_batch_set_config", "pcls_batch_get_config",
            "pcls_batch_step", "pcls_batch_capture", "pcls_batch_replay", "pcls_batch_autotune",
-           "pcls_batch_destroy"]
+           "pcls_batch_destroy", "pcls_valu_probe"]
 
 
 class PclsError(RuntimeError):
@@ -98,6 +98,8 @@ def load_library():
     L.pcls_destroy.argtypes = [P]
     L.pcls_last_error.restype = ctypes.c_char_p
     L.pcls_last_error.argtypes = []
+    L.pcls_valu_probe.restype = i32
+    L.pcls_valu_probe.argtypes = [i32, i32, vp, vp]
     _lib = L
     return L
 
@@ -288,3 +290,19 @@ def solve(problem: Problem, R: int, steps: int, lr: float = 0.1, seed: int = 0):
     problem.step(X, R, lr, steps)
     assign, unsat, best = problem.extract(X, R)
     return X, assign, unsat, best
+
+
+def valu_issue_rate(blocks: int = 8192, iters: int = 2048, device="cuda:0") -> float:
+    """Measured VALU instruction-issue ceiling of the device, in wave64
+    instructions per second (timed launch of pcls_valu_probe after a warm-up)."""
+    import torch
+    out = torch.empty(blocks * 256, dtype=torch.float32, device=device)
+    L = load_library()
+    st = _stream()
+    check(L.pcls_valu_probe(blocks, iters, _tptr(out), st))
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    check(L.pcls_valu_probe(blocks, iters, _tptr(out), st))
+    e1.record()
+    torch.cuda.synchronize()
+    return blocks * 4 * iters * 64 / (e0.elapsed_time(e1) / 1e3)
