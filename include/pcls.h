@@ -19,9 +19,11 @@
  *  - Restart state X is float32, laid out [n][R_pad] (restart index
  *    contiguous), R_pad = round_up(R, 64).  Columns r >= R are padding: the
  *    library may read and write them and their content is unspecified.
- *  - Gradients and objectives are accumulated in exact fixed point, so results
- *    are bitwise reproducible and independent of launch shape; the fixed-point
- *    scales are chosen per problem (see pcls_info) so that no sum overflows.
+ *  - Gradients are accumulated in exact fixed point, so they (and hence the
+ *    iterates) are bitwise reproducible and independent of the launch shape;
+ *    objectives are FP32 sums over fixed work chunks added in exact fixed point,
+ *    bitwise reproducible for a given launch shape.  The fixed-point scales are
+ *    chosen per problem (see pcls_info) so that no sum overflows.
  *  - All device pointers are caller-owned (hipMalloc'd or torch tensors).
  *    Every device operation is enqueued asynchronously on the given HIP
  *    stream (hipStream_t passed as void*; NULL = the null stream); the host

@@ -179,25 +179,20 @@ struct Fetched {
   float w;
 };
 
-template <int J>
+template <int J, int KMAX>
 __device__ __forceinline__ void fetch_pair(const ProblemDev& P, const Segment& S, int c_local, int lig,
                                            Fetched<J>& f) {
-  if (c_local >= S.c_count) {
+  // A lane past the segment fetches its last pair (valid memory, no branch); the
+  // caller skips evaluating it.
+  const int cl = min(c_local, S.c_count - 1);
+  // Buffer loads: the slot's column offset is wave-uniform (scalar soffset) and
+  // the lane's offset is one 32-bit register shared by every slot.
+  const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+      (void*)(P.litT + S.lit_base), (short)0, KMAX * S.c_count * 4, 0x00020000);
+  const unsigned voff = ((unsigned)(lig * J) * (unsigned)S.c_count + (unsigned)cl) * 4u;
 #pragma unroll
-    for (int j = 0; j < J; ++j) f.code[j] = -1;
-    f.cls = S.cls_fixed >= 0 ? S.cls_fixed : 0;
-    f.w = 0.f;
-    return;
-  }
-  // one 32-bit lane offset shared by every slot; the slot's column start is
-  // wave-uniform, so each load is a scalar base plus the same vector offset
-  const unsigned off = (unsigned)(lig * J) * (unsigned)S.c_count + (unsigned)c_local;
-#pragma unroll
-  for (int j = 0; j < J; ++j) {
-    const int32_t* col = P.litT + S.lit_base + (size_t)j * S.c_count;
-    f.code[j] = col[off];
-  }
-  const int c = S.c_begin + c_local;
+  for (int j = 0; j < J; ++j) f.code[j] = __builtin_amdgcn_raw_buffer_load_b32(rs, voff, j * S.c_count * 4, 0);
+  const int c = S.c_begin + cl;
   f.cls = S.cls_fixed >= 0 ? S.cls_fixed : P.c_cls[c];
   f.w = P.unit_weights ? 1.f : P.c_w[c];
 }
@@ -220,7 +215,7 @@ __device__ __forceinline__ ProdParams prod_params(kptr<ClassRec> classes, int cl
 
 template <int NN, int KMAX, int G, class AT>
 __device__ __forceinline__ void prod_pair(const Fetched<KMAX / G>& fp, int lig, int t, int logT, const float* xs, AT* gs,
-                                          long long& facc, float gsc, float fsc, const ProdParams& pp) {
+                                          float& fchunk, float gsc, float fsc, const ProdParams& pp) {
   constexpr int J = KMAX / G;
   constexpr bool kExact = KMAX <= 8;  // buckets up to 8 hold a single length
   const int T = 1 << logT;
@@ -261,7 +256,7 @@ __device__ __forceinline__ void prod_pair(const Fetched<KMAX / G>& fp, int lig, 
   if (lig == 0) {
     float fe = c1 * (run1 * xq1);
     if constexpr (NN == 2) fe = fmaf(c2, run2 * xq2, fe);
-    facc += fixed_term(fp.w * fsc * fe);
+    fchunk = fmaf(fp.w * fsc, fe, fchunk);
   }
   const float s1 = c1 * b1 * (fp.w * gsc) * xp1;
   const float s2 = -0.5f * c2 * (fp.w * gsc) * xp2;
@@ -284,7 +279,7 @@ __device__ __forceinline__ void prod_pair(const Fetched<KMAX / G>& fp, int lig, 
 // record and the node table are read with scalar loads.
 template <int KMAX, int G, class AT>
 __device__ __forceinline__ void dft_pair(const ProblemDev& P, int m_max, int cls, const Fetched<KMAX / G>& fp,
-                                         int lig, int t, int logT, const float* xs, AT* gs, long long& facc,
+                                         int lig, int t, int logT, const float* xs, AT* gs, float& fchunk,
                                          float gsc, float fsc) {
   constexpr int J = KMAX / G;
   constexpr bool kExact = KMAX <= 8;  // buckets up to 8 hold a single length
@@ -357,7 +352,7 @@ __device__ __forceinline__ void dft_pair(const ProblemDev& P, int m_max, int cls
       }
     }
   }
-  if (lig == 0) facc += fixed_term(fp.w * fsc * fe);
+  if (lig == 0) fchunk = fmaf(fp.w * fsc, fe, fchunk);
 #pragma unroll
   for (int j = 0; j < J; ++j) {
     if (kExact || fp.code[j] != -1) {
@@ -379,7 +374,7 @@ __device__ __forceinline__ void dft_pair(const ProblemDev& P, int m_max, int cls
 // Every update is a convex combination, so no cancellation arises.
 template <int KMAX, class AT>
 __device__ __forceinline__ void pmf_pair(const ProblemDev& P, int cls, const Fetched<KMAX>& fp, int t, int logT,
-                                         const float* xs, AT* gs, long long& facc, float gsc, float fsc) {
+                                         const float* xs, AT* gs, float& fchunk, float gsc, float fsc) {
   constexpr int J = KMAX;  // buckets up to 8 hold a single length
   constexpr int W = kPmfWindow;
   kptr<ClassRec> classes = kconst(P.classes);
@@ -404,7 +399,7 @@ __device__ __forceinline__ void pmf_pair(const ProblemDev& P, int cls, const Fet
   float fe = 0.f;
 #pragma unroll
   for (int c = 0; c < W; ++c) fe = fmaf(d[c], q[c], fe);
-  facc += fixed_term(fp.w * fsc * fe);
+  fchunk = fmaf(fp.w * fsc, fe, fchunk);
   // dFE/dy_i = -h dFE/dpi_i
   const float coef = -h * (fp.w * gsc);
   float* lam = d;
@@ -468,7 +463,7 @@ __device__ __forceinline__ void run_segment(const ProblemDev& P, const Segment& 
   };
   auto fetch = [&](int b, FetchedU<J, U>& f) {
 #pragma unroll
-    for (int u = 0; u < U; ++u) fetch_pair<J>(P, S, b + u * per_wave + sub, lig, f.p[u]);
+    for (int u = 0; u < U; ++u) fetch_pair<J, KMAX>(P, S, b + u * per_wave + sub, lig, f.p[u]);
   };
   int base = claim();
   FetchedU<J, U> cur;
@@ -477,6 +472,10 @@ __device__ __forceinline__ void run_segment(const ProblemDev& P, const Segment& 
     const int nbase = claim();
     FetchedU<J, U> nxt;
     fetch(nbase, nxt);
+    // A chunk (aligned, fixed pairs per lane, fixed order) sums its objective
+    // terms in FP32 and adds one exact fixed-point term: the result does not
+    // depend on which wave claimed the chunk.
+    float fchunk = 0.f;
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const int b_u = base + u * per_wave;
@@ -491,18 +490,19 @@ __device__ __forceinline__ void run_segment(const ProblemDev& P, const Segment& 
         if constexpr (KIND == KIND_DFT) {
           if (chunk_uni) {
             kptr<ClassRec> cr = kconst(P.classes);
-            dft_pair<KMAX, G>(P, cr[c0].n_nodes, c0, fp, lig, t, logT, xs, gs, facc, gsc, fsc);
+            dft_pair<KMAX, G>(P, cr[c0].n_nodes, c0, fp, lig, t, logT, xs, gs, fchunk, gsc, fsc);
           } else {
-            dft_pair<KMAX, G>(P, S.m_max, fp.cls, fp, lig, t, logT, xs, gs, facc, gsc, fsc);
+            dft_pair<KMAX, G>(P, S.m_max, fp.cls, fp, lig, t, logT, xs, gs, fchunk, gsc, fsc);
           }
         } else if constexpr (KIND == KIND_PMF) {
-          pmf_pair<KMAX>(P, chunk_uni ? c0 : fp.cls, fp, t, logT, xs, gs, facc, gsc, fsc);
+          pmf_pair<KMAX>(P, chunk_uni ? c0 : fp.cls, fp, t, logT, xs, gs, fchunk, gsc, fsc);
         } else {
           const ProdParams pp = uni ? pp_uni : prod_params(classes, chunk_uni ? c0 : fp.cls);
-          prod_pair<KIND == KIND_PROD2 ? 2 : 1, KMAX, G>(fp, lig, t, logT, xs, gs, facc, gsc, fsc, pp);
+          prod_pair<KIND == KIND_PROD2 ? 2 : 1, KMAX, G>(fp, lig, t, logT, xs, gs, fchunk, gsc, fsc, pp);
         }
       }
     }
+    facc += fixed_term(fchunk);
     cur = nxt;
     base = nbase;
   }

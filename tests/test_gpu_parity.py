@@ -292,7 +292,10 @@ def test_state_too_large_for_lds_is_reported():
 
 def test_gradient_bitwise_deterministic_across_launches():
     """Fixed-point accumulation is exact and order-independent: the gradient is
-    bitwise identical across repeated launches and across tile sizes."""
+    bitwise identical across repeated launches, dynamic work claims and tile
+    sizes; the objective (FP32 sums over each fixed work chunk, then exact fixed
+    point) is bitwise identical for a given launch shape and agrees to FP32
+    rounding across shapes."""
     inst = synth.c2_mixed(seed=6, n=500, n_or=1500, n_xor=150, n_card=50)
     log("case determinism")
     prob = pcls.Problem.from_instance(inst)
@@ -306,7 +309,8 @@ def test_gradient_bitwise_deterministic_across_launches():
         outs.append((obj.cpu().numpy(), grad.cpu().numpy()))
     for o, g in outs[1:]:
         assert np.array_equal(g[:, :R], outs[0][1][:, :R])
-        assert np.array_equal(o, outs[0][0])  # the objective is an exact fixed-point sum too
+        np.testing.assert_allclose(o, outs[0][0], rtol=1e-6, atol=1e-6 * inst.m)
+    assert np.array_equal(outs[3][0], outs[0][0])  # same launch shape: same objective bits
 
 
 @pytest.mark.parametrize("bits", [32, 64])
