@@ -417,6 +417,80 @@ __device__ __forceinline__ void pmf_pair(const ProblemDev& P, int cls, const Fet
   }
 }
 
+// Per-lane objective partial sums (exact integers): `own` for restart
+// lane mod T; `even` and `odd` for restarts 2 t2 and 2 t2 + 1 of the paths that
+// give a lane two adjacent restarts (t2 = lane mod T/2).
+struct ObjAcc {
+  long long own, even, odd;
+};
+
+// Two restarts per lane (short product constraints, tiles of T >= 2): the
+// codes, the address decode, the claim and the loop control are shared by two
+// literal-evaluations; x of both restarts arrives in one 8-byte LDS read and the
+// second gradient term goes to the next LDS word.
+template <int NN, int KMAX, class AT>
+__device__ __forceinline__ void prod_pair_r2(const Fetched<KMAX>& fp, int t2, int logT, const float* xs, AT* gs,
+                                             float& fca, float& fcb, float gsc, float fsc, const ProdParams& pp) {
+  constexpr int J = KMAX;  // one lane per pair, every slot filled (buckets up to 8 hold one length)
+  const float a1 = pp.a, b1 = pp.b, c1 = pp.c1, c2 = pp.c2;
+  int el[J];
+  float fa1[J], fb1[J], fa2[J], fb2[J];
+#pragma unroll
+  for (int j = 0; j < J; ++j) {
+    el[j] = lit_elem(fp.code[j], logT, 2 * t2);
+    const float2 xv = *reinterpret_cast<const float2*>(xs + el[j]);
+    const unsigned sb = lit_sign(fp.code[j]);
+    const float ya = flip(xv.x, sb), yb = flip(xv.y, sb);
+    fa1[j] = fmaf(b1, ya, a1);
+    fb1[j] = fmaf(b1, yb, a1);
+    if constexpr (NN == 2) {
+      fa2[j] = fmaf(-0.5f, ya, 0.5f);
+      fb2[j] = fmaf(-0.5f, yb, 0.5f);
+    }
+  }
+  float pa1[J], pb1[J], pa2[J], pb2[J];
+  float ra1 = 1.f, rb1 = 1.f, ra2 = 1.f, rb2 = 1.f;
+#pragma unroll
+  for (int j = 0; j < J; ++j) {
+    pa1[j] = ra1;
+    pb1[j] = rb1;
+    ra1 *= fa1[j];
+    rb1 *= fb1[j];
+    if constexpr (NN == 2) {
+      pa2[j] = ra2;
+      pb2[j] = rb2;
+      ra2 *= fa2[j];
+      rb2 *= fb2[j];
+    }
+  }
+  float fea = c1 * ra1, feb = c1 * rb1;
+  if constexpr (NN == 2) {
+    fea = fmaf(c2, ra2, fea);
+    feb = fmaf(c2, rb2, feb);
+  }
+  const float wf = fp.w * fsc;
+  fca = fmaf(wf, fea, fca);
+  fcb = fmaf(wf, feb, fcb);
+  const float s1 = c1 * b1 * (fp.w * gsc);
+  const float s2 = -0.5f * c2 * (fp.w * gsc);
+  float sa1 = 1.f, sb1 = 1.f, sa2 = 1.f, sb2 = 1.f;
+#pragma unroll
+  for (int j = J - 1; j >= 0; --j) {
+    float ga = s1 * pa1[j] * sa1, gb = s1 * pb1[j] * sb1;
+    sa1 *= fa1[j];
+    sb1 *= fb1[j];
+    if constexpr (NN == 2) {
+      ga = fmaf(s2 * pa2[j], sa2, ga);
+      gb = fmaf(s2 * pb2[j], sb2, gb);
+      sa2 *= fa2[j];
+      sb2 *= fb2[j];
+    }
+    const unsigned sg = lit_sign(fp.code[j]);
+    FixedAcc<AT>::add(&gs[el[j]], flip(ga, sg));
+    FixedAcc<AT>::add(&gs[el[j] + 1], flip(gb, sg));
+  }
+}
+
 // Pairs each lane takes per claim: short product constraints are cheap, so a
 // lane takes several of them per claim, which amortises the claim, the fetch
 // addressing and the loop control over more literals.
@@ -432,9 +506,67 @@ struct FetchedU {
   Fetched<J> p[U];
 };
 
+// The two-restarts-per-lane variant of run_segment for short product kinds.
+template <int KIND, int KMAX, class AT>
+__device__ __forceinline__ void run_segment_r2(const ProblemDev& P, const Segment& S, const float* xs, AT* gs,
+                                               ObjAcc& facc, float gsc, float fsc, int tid, int logT, int* ctr) {
+  constexpr int J = KMAX;
+  constexpr int U = J <= 4 ? 2 : 1;
+  asm volatile("" : "+v"(tid));
+  const int lane = tid & (kWave - 1);
+  const int t2 = lane & ((1 << (logT - 1)) - 1);
+  const int sub = lane >> (logT - 1);
+  const int per_wave = kWave >> (logT - 1);
+  kptr<ClassRec> classes = kconst(P.classes);
+  const bool uni = S.cls_fixed >= 0;
+  ProdParams pp_uni{};
+  if (uni) pp_uni = prod_params(classes, S.cls_fixed);
+  auto claim = [&]() {
+    int b = 0;
+    if (lane == 0) b = atomicAdd(ctr, U * per_wave);
+    return __builtin_amdgcn_readfirstlane(b);
+  };
+  auto fetch = [&](int b, FetchedU<J, U>& f) {
+#pragma unroll
+    for (int u = 0; u < U; ++u) fetch_pair<J, KMAX>(P, S, b + u * per_wave + sub, 0, f.p[u]);
+  };
+  int base = claim();
+  FetchedU<J, U> cur;
+  fetch(base, cur);
+  while (base < S.c_count) {
+    const int nbase = claim();
+    FetchedU<J, U> nxt;
+    fetch(nbase, nxt);
+    float fca = 0.f, fcb = 0.f;
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int b_u = base + u * per_wave;
+      if (u > 0 && b_u >= S.c_count) break;
+      const Fetched<J>& fp = cur.p[u];
+      const bool valid = b_u + sub < S.c_count;
+      const int c0 = __builtin_amdgcn_readfirstlane(fp.cls);
+      const bool chunk_uni = uni || !__any(valid && fp.cls != c0);
+      if (valid) {
+        const ProdParams pp = uni ? pp_uni : prod_params(classes, chunk_uni ? c0 : fp.cls);
+        prod_pair_r2<KIND == KIND_PROD2 ? 2 : 1, KMAX>(fp, t2, logT, xs, gs, fca, fcb, gsc, fsc, pp);
+      }
+    }
+    facc.even += fixed_term(fca);
+    facc.odd += fixed_term(fcb);
+    cur = nxt;
+    base = nbase;
+  }
+}
+
 template <int KIND, int KMAX, int MAXB, class AT>
 __device__ __forceinline__ void run_segment(const ProblemDev& P, const Segment& S, const float* xs, AT* gs,
-                                            long long& facc, float gsc, float fsc, int tid, int logT, int* ctr) {
+                                            ObjAcc& facc, float gsc, float fsc, int tid, int logT, int* ctr) {
+  if constexpr ((KIND == KIND_PROD1 || KIND == KIND_PROD2) && MAXB <= 7 && KMAX <= 8) {
+    if (logT >= 1) {
+      run_segment_r2<KIND, KMAX>(P, S, xs, gs, facc, gsc, fsc, tid, logT, ctr);
+      return;
+    }
+  }
   constexpr int G = group_size(KIND, KMAX);
   constexpr int LG = Log2<G>::v;
   constexpr int J = KMAX / G;
@@ -502,7 +634,7 @@ __device__ __forceinline__ void run_segment(const ProblemDev& P, const Segment& 
         }
       }
     }
-    facc += fixed_term(fchunk);
+    facc.own += fixed_term(fchunk);
     cur = nxt;
     base = nbase;
   }
@@ -540,7 +672,7 @@ __device__ __forceinline__ void run_segment(const ProblemDev& P, const Segment& 
 
 template <int MAXB, class AT>
 __device__ __forceinline__ void run_any_segment(const ProblemDev& P, const Segment& S, const float* xs, AT* gs,
-                                                long long& facc, float gsc, float fsc, int tid, int logT,
+                                                ObjAcc& facc, float gsc, float fsc, int tid, int logT,
                                                 int* ctr) {
   switch (S.kind * kNumBuckets + S.bucket) {
     PCLS_BUCKET_CASES(KIND_PROD1, PCLS_CASE)
@@ -606,7 +738,7 @@ __device__ __forceinline__ void resident_tile(const ProblemDev& P, const TileArg
   float F_last = 0.f;  // threads tid < T: last evaluated objective of restart r0 + tid
 
   for (int s = 0; s < A.n_steps; ++s) {
-    long long facc = 0;
+    ObjAcc facc{0, 0, 0};
     kptr<Segment> segs = kconst(P.segments);
     for (int sg = 0; sg < n_seg; ++sg) {
       const Segment S{segs[sg].kind,    segs[sg].bucket, segs[sg].c_begin,   segs[sg].c_count,
@@ -614,8 +746,21 @@ __device__ __forceinline__ void resident_tile(const ProblemDev& P, const TileArg
       run_any_segment<MAXB>(P, S, xs, gs, facc, A.gsc, A.fsc, tid, logT, ctr + sg);
     }
     // lanes with equal (lane mod T) hold the same restart; integer sums are exact
-    for (int o = T; o < kWave; o <<= 1) facc += __shfl_xor(facc, o);
-    if ((tid & (kWave - 1)) < T) atomicAdd(&Fs[t], (unsigned long long)facc);
+    for (int o = T; o < kWave; o <<= 1) facc.own += __shfl_xor(facc.own, o);
+    if ((tid & (kWave - 1)) < T) atomicAdd(&Fs[t], (unsigned long long)facc.own);
+    if constexpr (MAXB <= 7) {
+      if (logT >= 1) {  // two-restart lanes: restarts 2 t2 and 2 t2 + 1, t2 = lane mod T/2
+        for (int o = T >> 1; o < kWave; o <<= 1) {
+          facc.even += __shfl_xor(facc.even, o);
+          facc.odd += __shfl_xor(facc.odd, o);
+        }
+        const int l = tid & (kWave - 1);
+        if (l < (T >> 1)) {
+          atomicAdd(&Fs[2 * l], (unsigned long long)facc.even);
+          atomicAdd(&Fs[2 * l + 1], (unsigned long long)facc.odd);
+        }
+      }
+    }
     __syncthreads();
     if (tid < n_seg) ctr[tid] = 0;  // every wave has left the segment loops
     if (tid < T) {

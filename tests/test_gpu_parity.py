@@ -342,3 +342,33 @@ def test_valu_probe_measures_issue_rate():
     rate = pcls.valu_issue_rate(blocks=2048, iters=256)
     assert 5e10 < rate < 5e12, rate
     assert L.pcls_valu_probe(0, 16, pcls._tptr(out), pcls._stream()) == pcls.PCLS_E_INVALID
+
+
+@pytest.mark.parametrize("T", [2, 4, 8])
+def test_short_types_two_restart_lanes(T):
+    """Every type with k <= 8 (products, two-node products, count windows, DFT)
+    at tile widths T >= 2, where short product constraints take two adjacent
+    restarts per lane: against the oracle, and gradients bitwise equal to the
+    one-restart-per-lane path (T = 1)."""
+    inst = synth.mixed_small(n=80, seed=31, kmax=8, count=400)
+    log(f"case short types T={T} m={inst.m}")
+    prob = pcls.Problem.from_instance(inst)
+    kinds = dict(zip(pcls.KIND_NAMES, prob.info().cons_by_kind))
+    assert kinds["prod1"] > 0 and kinds["prod2"] > 0 and kinds["pmf"] > 0
+    R = 150
+    x = corner_mix(np.random.default_rng(31), R, inst.n)
+    X = prob.state_from_rows(x)
+    prob.set_launch(T, 512)
+    obj, grad = prob.evaluate(X, R)
+    ref = oracle_for(inst).evaluate(rows_of(X, R), method=N.PMF)
+    assert_obj_grad(obj.cpu().numpy(), grad[:, :R].T.cpu().numpy(), ref, what=f"short T={T}", inst=inst)
+    prob.set_launch(1, 512)
+    _, g1 = prob.evaluate(X, R)
+    assert torch.equal(grad[:, :R], g1[:, :R])
+    # and a few steps agree bitwise too
+    X1, X2 = X.clone(), X.clone()
+    prob.set_launch(T, 512)
+    prob.step(X1, R, 0.1, 5)
+    prob.set_launch(1, 512)
+    prob.step(X2, R, 0.1, 5)
+    assert torch.equal(X1[:, :R], X2[:, :R])
