@@ -199,7 +199,19 @@ __device__ __forceinline__ void fetch_pair(const ProblemDev& P, const Segment& S
 
 // Literal decode: LDS element of (variable, restart t) and the sign bit, which
 // is XORed onto x (y = s x) and onto the gradient term (dF/dx = s dF/dy).
-__device__ __forceinline__ int lit_elem(int code, int logT, int t) { return ((code & 0x7fffffff) << logT) | t; }
+// Byte offset of (variable, restart t) in an array of 4-byte elements laid out
+// [variable][T]: shifting by log2 T + 2 >= 2 drops the sign bit.  The gradient
+// array uses the same offset scaled by its element size.
+__device__ __forceinline__ unsigned lit_off(int code, int logT, int t) {
+  return ((unsigned)code << (logT + 2)) | ((unsigned)t << 2);
+}
+__device__ __forceinline__ float x_at(const float* xs, unsigned off) {
+  return *reinterpret_cast<const float*>(reinterpret_cast<const char*>(xs) + off);
+}
+template <class AT>
+__device__ __forceinline__ AT* g_at(AT* gs, unsigned off) {
+  return reinterpret_cast<AT*>(reinterpret_cast<char*>(gs) + off * (unsigned)(sizeof(AT) / 4));
+}
 __device__ __forceinline__ unsigned lit_sign(int code) { return (unsigned)code & 0x80000000u; }
 __device__ __forceinline__ float flip(float v, unsigned sb) { return __uint_as_float(__float_as_uint(v) ^ sb); }
 
@@ -221,7 +233,7 @@ __device__ __forceinline__ void prod_pair(const Fetched<KMAX / G>& fp, int lig, 
   const int T = 1 << logT;
   const float a1 = pp.a, b1 = pp.b, c1 = pp.c1, c2 = pp.c2;
 
-  int el[J];
+  unsigned el[J];
   float f1[J], f2[J];
 #pragma unroll
   for (int j = 0; j < J; ++j) {
@@ -230,8 +242,8 @@ __device__ __forceinline__ void prod_pair(const Fetched<KMAX / G>& fp, int lig, 
     f1[j] = 1.f;
     f2[j] = 1.f;
     if (kExact || code != -1) {
-      el[j] = lit_elem(code, logT, t);
-      const float y = flip(xs[el[j]], lit_sign(code));
+      el[j] = lit_off(code, logT, t);
+      const float y = flip(x_at(xs, el[j]), lit_sign(code));
       f1[j] = fmaf(b1, y, a1);
       if constexpr (NN == 2) f2[j] = fmaf(-0.5f, y, 0.5f);
     }
@@ -269,7 +281,7 @@ __device__ __forceinline__ void prod_pair(const Fetched<KMAX / G>& fp, int lig, 
       g = fmaf(s2 * pre2[j], suf2, g);
       suf2 *= f2[j];
     }
-    if (kExact || fp.code[j] != -1) FixedAcc<AT>::add(&gs[el[j]], flip(g, lit_sign(fp.code[j])));
+    if (kExact || fp.code[j] != -1) FixedAcc<AT>::add(g_at(gs, el[j]), flip(g, lit_sign(fp.code[j])));
   }
 }
 
@@ -290,7 +302,7 @@ __device__ __forceinline__ void dft_pair(const ProblemDev& P, int m_max, int cls
   const int node_off = classes[cls].node_off;
   const int nn = classes[cls].n_nodes;
 
-  int el[J];
+  unsigned el[J];
   float y[J], g[J];
 #pragma unroll
   for (int j = 0; j < J; ++j) {
@@ -299,8 +311,8 @@ __device__ __forceinline__ void dft_pair(const ProblemDev& P, int m_max, int cls
     y[j] = 1.f;
     g[j] = 0.f;
     if (kExact || code != -1) {
-      el[j] = lit_elem(code, logT, t);
-      y[j] = flip(xs[el[j]], lit_sign(code));
+      el[j] = lit_off(code, logT, t);
+      y[j] = flip(x_at(xs, el[j]), lit_sign(code));
     }
   }
   float fe = 0.f;
@@ -357,7 +369,7 @@ __device__ __forceinline__ void dft_pair(const ProblemDev& P, int m_max, int cls
   for (int j = 0; j < J; ++j) {
     if (kExact || fp.code[j] != -1) {
       const float gv = (fp.w * gsc) * g[j];
-      FixedAcc<AT>::add(&gs[el[j]], flip(gv, lit_sign(fp.code[j])));
+      FixedAcc<AT>::add(g_at(gs, el[j]), flip(gv, lit_sign(fp.code[j])));
     }
   }
 }
@@ -382,13 +394,13 @@ __device__ __forceinline__ void pmf_pair(const ProblemDev& P, int cls, const Fet
   float d[W] = {nd[0].ar, nd[0].ai, nd[0].br, nd[0].bi};
   const float h = nd[0].wr;
 
-  int el[J];
+  unsigned el[J];
   float pi[J], pre[J][W];
   float q[W] = {1.f, 0.f, 0.f, 0.f};
 #pragma unroll
   for (int j = 0; j < J; ++j) {
-    el[j] = lit_elem(fp.code[j], logT, t);
-    const float y = flip(xs[el[j]], lit_sign(fp.code[j]));
+    el[j] = lit_off(fp.code[j], logT, t);
+    const float y = flip(x_at(xs, el[j]), lit_sign(fp.code[j]));
     pi[j] = fmaf(-h, y, 0.5f);
 #pragma unroll
     for (int c = 0; c < W; ++c) pre[j][c] = q[c];
@@ -413,7 +425,7 @@ __device__ __forceinline__ void pmf_pair(const ProblemDev& P, int cls, const Fet
     }
 #pragma unroll
     for (int c = 0; c < W; ++c) lam[c] = fmaf(pi[j], diff[c], lam[c]);
-    FixedAcc<AT>::add(&gs[el[j]], flip(coef * gp, lit_sign(fp.code[j])));
+    FixedAcc<AT>::add(g_at(gs, el[j]), flip(coef * gp, lit_sign(fp.code[j])));
   }
 }
 
@@ -433,12 +445,12 @@ __device__ __forceinline__ void prod_pair_r2(const Fetched<KMAX>& fp, int t2, in
                                              float& fca, float& fcb, float gsc, float fsc, const ProdParams& pp) {
   constexpr int J = KMAX;  // one lane per pair, every slot filled (buckets up to 8 hold one length)
   const float a1 = pp.a, b1 = pp.b, c1 = pp.c1, c2 = pp.c2;
-  int el[J];
+  unsigned el[J];
   float fa1[J], fb1[J], fa2[J], fb2[J];
 #pragma unroll
   for (int j = 0; j < J; ++j) {
-    el[j] = lit_elem(fp.code[j], logT, 2 * t2);
-    const float2 xv = *reinterpret_cast<const float2*>(xs + el[j]);
+    el[j] = lit_off(fp.code[j], logT, 2 * t2);
+    const float2 xv = *reinterpret_cast<const float2*>(reinterpret_cast<const char*>(xs) + el[j]);
     const unsigned sb = lit_sign(fp.code[j]);
     const float ya = flip(xv.x, sb), yb = flip(xv.y, sb);
     fa1[j] = fmaf(b1, ya, a1);
@@ -486,8 +498,9 @@ __device__ __forceinline__ void prod_pair_r2(const Fetched<KMAX>& fp, int t2, in
       sb2 *= fb2[j];
     }
     const unsigned sg = lit_sign(fp.code[j]);
-    FixedAcc<AT>::add(&gs[el[j]], flip(ga, sg));
-    FixedAcc<AT>::add(&gs[el[j] + 1], flip(gb, sg));
+    AT* gp = g_at(gs, el[j]);
+    FixedAcc<AT>::add(gp, flip(ga, sg));
+    FixedAcc<AT>::add(gp + 1, flip(gb, sg));
   }
 }
 
