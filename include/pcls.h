@@ -268,6 +268,24 @@ int32_t pcls_batch_destroy(pcls_batch* b);
 /* Free the host plan; never frees caller memory. */
 int32_t pcls_destroy(pcls_problem* p);
 
+/*
+ * Per-constraint gradient statistic for adaptive weighting (Case Studies,
+ * "Redundant Constraint Effect", and Conclusions: weights informed by
+ * per-constraint gradient magnitudes).  For every constraint c,
+ *   d_out[c] = sum over restarts r < R of sum over literals i of c of
+ *              (dFE_c/dy_i at x_r)^2,
+ * unweighted (y_i the literal value), in the caller's constraint order.
+ *   d_x   : device [n_vars][R_pad] state, as for pcls_evaluate.
+ *   d_acc : device scratch of n_cons 64-bit words (caller-owned, overwritten).
+ *   d_out : device float[n_cons].
+ * Sums are exact 64-bit fixed point at scale 2^s, s = min(40, 60 - ceil(log2(R
+ * max_len + 1))), so the result is deterministic; constant constraints report
+ * 0.  Asynchronous on `stream`.  PCLS_E_INVALID for R < 1 or a NULL pointer
+ * (n_cons > 0); PCLS_E_UNSUPPORTED when one restart's state does not fit in LDS.
+ */
+int32_t pcls_constraint_grad_stats(const pcls_problem* p, int32_t R, const float* d_x, uint64_t* d_acc,
+                                   float* d_out, void* stream);
+
 /* Thread-local description of the last error; valid until the next call. */
 const char* pcls_last_error(void);
 

@@ -223,6 +223,42 @@ long orc_eval_problem(int n, int m, const int32_t *row_ptr, const int32_t *lit, 
     return n_pmf;
 }
 
+/*
+ * Per-constraint gradient statistic behind adaptive weighting (Case Studies,
+ * "Redundant Constraint Effect": weights informed by per-constraint gradient
+ * magnitudes): out[c] = sum over the R restarts of sum_i (dFE_c/dy_i)^2, the
+ * unweighted squared gradient of constraint c with respect to its literal
+ * values.  PMF route (stable at every length).
+ */
+void orc_constraint_grad_sq(int n, int m, const int32_t *row_ptr, const int32_t *lit, const double *sp_all,
+                            int R, const double *x, double *out)
+{
+    int kmax = 0;
+    for (int c = 0; c < m; ++c) {
+        int k = row_ptr[c + 1] - row_ptr[c];
+        if (k > kmax) kmax = k;
+    }
+    double *y = (double *)malloc(sizeof(double) * (size_t)(kmax + 1));
+    double *gc = (double *)malloc(sizeof(double) * (size_t)(kmax + 1));
+    for (int c = 0; c < m; ++c) out[c] = 0.0;
+    for (int r = 0; r < R; ++r) {
+        const double *xr = x + (size_t)r * n;
+        for (int c = 0; c < m; ++c) {
+            int b = row_ptr[c], k = row_ptr[c + 1] - b;
+            for (int i = 0; i < k; ++i) {
+                int l = lit[b + i];
+                int v = (l > 0 ? l : -l) - 1;
+                y[i] = (l > 0 ? 1.0 : -1.0) * xr[v];
+            }
+            double fe;
+            orc_eval_constraint(k, sp_all + b + c, NULL, y, ORC_PMF, &fe, gc, NULL);
+            for (int i = 0; i < k; ++i) out[c] += gc[i] * gc[i];
+        }
+    }
+    free(y);
+    free(gc);
+}
+
 /* Projected gradient step (Background, "Satisfaction as Optimisation"). */
 void orc_step(long count, const double *x, const double *grad, double lr, double *x_out)
 {

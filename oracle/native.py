@@ -57,6 +57,8 @@ def lib():
         L.orc_eval_problem.restype = ctypes.c_long
         L.orc_eval_problem.argtypes = [ctypes.c_int, ctypes.c_int, ip, ip, dp, dp, dp, ctypes.c_int, dp,
                                        dp, dp, dp, dp, ctypes.c_int]
+        L.orc_constraint_grad_sq.restype = None
+        L.orc_constraint_grad_sq.argtypes = [ctypes.c_int, ctypes.c_int, ip, ip, dp, ctypes.c_int, dp, dp]
         L.orc_step.restype = None
         L.orc_step.argtypes = [ctypes.c_long, dp, dp, ctypes.c_double, dp]
         L.orc_extract.restype = None
@@ -168,6 +170,14 @@ class OracleProblem:
                                        _p(self.weight), R, _p(x), _p(obj), _p(grad), _p(so), _p(sg),
                                        method)
         return {"obj": obj, "grad": grad, "sig_obj": so, "sig_grad": sg, "n_pmf": int(n_pmf)}
+
+    def constraint_grad_sq(self, x):
+        """x: [R][n] -> [m]: per constraint, sum over rows of sum_i (dFE_c/dy_i)^2."""
+        x = _f64(np.atleast_2d(x))
+        out = np.zeros(self.m)
+        lib().orc_constraint_grad_sq(self.n, self.m, _p(self.row_ptr, ctypes.c_int32), _p(self.lit, ctypes.c_int32),
+                                     _p(self.sp_all), x.shape[0], _p(x), _p(out))
+        return out
 
     def extract(self, x):
         x = _f64(np.atleast_2d(x))

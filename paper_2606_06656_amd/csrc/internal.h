@@ -102,6 +102,7 @@ struct ProblemDev {
   int32_t unit_weights;          // all weights 1.0
   int32_t max_k;
   const int32_t* occ;            // per variable: occurrences in non-constant constraints
+  const int32_t* perm;           // planned index -> caller's constraint index
 };
 
 }  // namespace pcls

@@ -212,6 +212,19 @@ template <class AT>
 __device__ __forceinline__ AT* g_at(AT* gs, unsigned off) {
   return reinterpret_cast<AT*>(reinterpret_cast<char*>(gs) + off * (unsigned)(sizeof(AT) / 4));
 }
+
+// Where a pair's per-literal gradient terms go: the tile's fixed-point LDS
+// accumulator (GradSink), or a per-lane sum of squares (SquareSink, for the
+// per-constraint gradient statistics).
+template <class AT>
+struct GradSink {
+  AT* gs;
+  __device__ __forceinline__ void add(unsigned off, float v) { FixedAcc<AT>::add(g_at(gs, off), v); }
+};
+struct SquareSink {
+  float acc;
+  __device__ __forceinline__ void add(unsigned, float v) { acc = fmaf(v, v, acc); }
+};
 __device__ __forceinline__ unsigned lit_sign(int code) { return (unsigned)code & 0x80000000u; }
 __device__ __forceinline__ float flip(float v, unsigned sb) { return __uint_as_float(__float_as_uint(v) ^ sb); }
 
@@ -225,8 +238,8 @@ __device__ __forceinline__ ProdParams prod_params(kptr<ClassRec> classes, int cl
   return {classes[cls].a, classes[cls].b, classes[cls].c1, classes[cls].c2};
 }
 
-template <int NN, int KMAX, int G, class AT>
-__device__ __forceinline__ void prod_pair(const Fetched<KMAX / G>& fp, int lig, int t, int logT, const float* xs, AT* gs,
+template <int NN, int KMAX, int G, class SK>
+__device__ __forceinline__ void prod_pair(const Fetched<KMAX / G>& fp, int lig, int t, int logT, const float* xs, SK& sink,
                                           float& fchunk, float gsc, float fsc, const ProdParams& pp) {
   constexpr int J = KMAX / G;
   constexpr bool kExact = KMAX <= 8;  // buckets up to 8 hold a single length
@@ -281,7 +294,7 @@ __device__ __forceinline__ void prod_pair(const Fetched<KMAX / G>& fp, int lig, 
       g = fmaf(s2 * pre2[j], suf2, g);
       suf2 *= f2[j];
     }
-    if (kExact || fp.code[j] != -1) FixedAcc<AT>::add(g_at(gs, el[j]), flip(g, lit_sign(fp.code[j])));
+    if (kExact || fp.code[j] != -1) sink.add(el[j], flip(g, lit_sign(fp.code[j])));
   }
 }
 
@@ -289,9 +302,9 @@ __device__ __forceinline__ void prod_pair(const Fetched<KMAX / G>& fp, int lig, 
 // dFE/dy_i = sum_m Re(2 chat_m beta_m prod_{j != i}(alpha_m + beta_m y_j)) [+ chat_{K/2} prod_{j != i} y_j].
 // cls is the pair's class; when the caller passes a wave-uniform value the class
 // record and the node table are read with scalar loads.
-template <int KMAX, int G, class AT>
+template <int KMAX, int G, class SK>
 __device__ __forceinline__ void dft_pair(const ProblemDev& P, int m_max, int cls, const Fetched<KMAX / G>& fp,
-                                         int lig, int t, int logT, const float* xs, AT* gs, float& fchunk,
+                                         int lig, int t, int logT, const float* xs, SK& sink, float& fchunk,
                                          float gsc, float fsc) {
   constexpr int J = KMAX / G;
   constexpr bool kExact = KMAX <= 8;  // buckets up to 8 hold a single length
@@ -369,7 +382,7 @@ __device__ __forceinline__ void dft_pair(const ProblemDev& P, int m_max, int cls
   for (int j = 0; j < J; ++j) {
     if (kExact || fp.code[j] != -1) {
       const float gv = (fp.w * gsc) * g[j];
-      FixedAcc<AT>::add(g_at(gs, el[j]), flip(gv, lit_sign(fp.code[j])));
+      sink.add(el[j], flip(gv, lit_sign(fp.code[j])));
     }
   }
 }
@@ -384,9 +397,9 @@ __device__ __forceinline__ void dft_pair(const ProblemDev& P, int m_max, int cls
 // dFE/dpi_i = sum_c pre_i[c] (lambda_{c+1} - lambda_c) (lambda_4 = 0) where pre_i
 // is q before literal i, then lambda_c <- lambda_c + pi_i (lambda_{c+1} - lambda_c).
 // Every update is a convex combination, so no cancellation arises.
-template <int KMAX, class AT>
+template <int KMAX, class SK>
 __device__ __forceinline__ void pmf_pair(const ProblemDev& P, int cls, const Fetched<KMAX>& fp, int t, int logT,
-                                         const float* xs, AT* gs, float& fchunk, float gsc, float fsc) {
+                                         const float* xs, SK& sink, float& fchunk, float gsc, float fsc) {
   constexpr int J = KMAX;  // buckets up to 8 hold a single length
   constexpr int W = kPmfWindow;
   kptr<ClassRec> classes = kconst(P.classes);
@@ -425,7 +438,7 @@ __device__ __forceinline__ void pmf_pair(const ProblemDev& P, int cls, const Fet
     }
 #pragma unroll
     for (int c = 0; c < W; ++c) lam[c] = fmaf(pi[j], diff[c], lam[c]);
-    FixedAcc<AT>::add(g_at(gs, el[j]), flip(coef * gp, lit_sign(fp.code[j])));
+    sink.add(el[j], flip(coef * gp, lit_sign(fp.code[j])));
   }
 }
 
@@ -571,10 +584,18 @@ __device__ __forceinline__ void run_segment_r2(const ProblemDev& P, const Segmen
   }
 }
 
-template <int KIND, int KMAX, int MAXB, class AT>
+// Per-constraint gradient statistics (statistics kernel only): 64-bit
+// fixed-point sums at scale 2^s of sum_i (dFE_c/dy_i)^2, planned order.
+struct StatsOut {
+  unsigned long long* acc;
+  float scale;
+};
+
+template <int KIND, int KMAX, int MAXB, class AT, bool ST = false>
 __device__ __forceinline__ void run_segment(const ProblemDev& P, const Segment& S, const float* xs, AT* gs,
-                                            ObjAcc& facc, float gsc, float fsc, int tid, int logT, int* ctr) {
-  if constexpr ((KIND == KIND_PROD1 || KIND == KIND_PROD2) && MAXB <= 7 && KMAX <= 8) {
+                                            ObjAcc& facc, float gsc, float fsc, int tid, int logT, int* ctr,
+                                            StatsOut so = {}) {
+  if constexpr (!ST && (KIND == KIND_PROD1 || KIND == KIND_PROD2) && MAXB <= 7 && KMAX <= 8) {
     if (logT >= 1) {
       run_segment_r2<KIND, KMAX>(P, S, xs, gs, facc, gsc, fsc, tid, logT, ctr);
       return;
@@ -631,19 +652,37 @@ __device__ __forceinline__ void run_segment(const ProblemDev& P, const Segment& 
       // one class: then its parameters are read once per wave with scalar loads
       const int c0 = __builtin_amdgcn_readfirstlane(fp.cls);  // lane 0 holds a valid pair
       const bool chunk_uni = uni || !__any(valid && fp.cls != c0);
-      if (valid) {
+      auto eval_pair = [&](auto& sink, const Fetched<J>& f) {
         if constexpr (KIND == KIND_DFT) {
           if (chunk_uni) {
             kptr<ClassRec> cr = kconst(P.classes);
-            dft_pair<KMAX, G>(P, cr[c0].n_nodes, c0, fp, lig, t, logT, xs, gs, fchunk, gsc, fsc);
+            dft_pair<KMAX, G>(P, cr[c0].n_nodes, c0, f, lig, t, logT, xs, sink, fchunk, gsc, fsc);
           } else {
-            dft_pair<KMAX, G>(P, S.m_max, fp.cls, fp, lig, t, logT, xs, gs, fchunk, gsc, fsc);
+            dft_pair<KMAX, G>(P, S.m_max, f.cls, f, lig, t, logT, xs, sink, fchunk, gsc, fsc);
           }
         } else if constexpr (KIND == KIND_PMF) {
-          pmf_pair<KMAX>(P, chunk_uni ? c0 : fp.cls, fp, t, logT, xs, gs, fchunk, gsc, fsc);
+          pmf_pair<KMAX>(P, chunk_uni ? c0 : f.cls, f, t, logT, xs, sink, fchunk, gsc, fsc);
         } else {
-          const ProdParams pp = uni ? pp_uni : prod_params(classes, chunk_uni ? c0 : fp.cls);
-          prod_pair<KIND == KIND_PROD2 ? 2 : 1, KMAX, G>(fp, lig, t, logT, xs, gs, fchunk, gsc, fsc, pp);
+          const ProdParams pp = uni ? pp_uni : prod_params(classes, chunk_uni ? c0 : f.cls);
+          prod_pair<KIND == KIND_PROD2 ? 2 : 1, KMAX, G>(f, lig, t, logT, xs, sink, fchunk, gsc, fsc, pp);
+        }
+      };
+      if constexpr (ST) {
+        // unweighted terms: weight 1 and scale 1 (gsc = 1 in this kernel)
+        float sq = 0.f;
+        if (valid) {
+          Fetched<J> f1 = fp;
+          f1.w = 1.f;
+          SquareSink sk{0.f};
+          eval_pair(sk, f1);
+          sq = sk.acc;
+        }
+        for (int o = 1 << logT; o < (G << logT); o <<= 1) sq += __shfl_xor(sq, o);  // the pair's G lanes
+        if (valid && lig == 0) atomicAdd(&so.acc[S.c_begin + b_u + sub], (unsigned long long)fixed_term(sq * so.scale));
+      } else {
+        if (valid) {
+          GradSink<AT> sk{gs};
+          eval_pair(sk, fp);
         }
       }
     }
@@ -678,15 +717,15 @@ __device__ __forceinline__ void run_segment(const ProblemDev& P, const Segment& 
   X(KIND, 6, 7)                          \
   X(KIND, 7, 8)
 
-#define PCLS_CASE(KIND, B, KMAX)                                     \
-  case (KIND)*kNumBuckets + (B):                                     \
-    if constexpr ((B) <= MAXB) run_segment<KIND, KMAX, MAXB>(P, S, xs, gs, facc, gsc, fsc, tid, logT, ctr); \
+#define PCLS_CASE(KIND, B, KMAX)                                                                    \
+  case (KIND)*kNumBuckets + (B):                                                                    \
+    if constexpr ((B) <= MAXB) run_segment<KIND, KMAX, MAXB, AT, ST>(P, S, xs, gs, facc, gsc, fsc, tid, logT, ctr, so); \
     break;
 
-template <int MAXB, class AT>
+template <int MAXB, class AT, bool ST = false>
 __device__ __forceinline__ void run_any_segment(const ProblemDev& P, const Segment& S, const float* xs, AT* gs,
                                                 ObjAcc& facc, float gsc, float fsc, int tid, int logT,
-                                                int* ctr) {
+                                                int* ctr, StatsOut so = {}) {
   switch (S.kind * kNumBuckets + S.bucket) {
     PCLS_BUCKET_CASES(KIND_PROD1, PCLS_CASE)
     PCLS_BUCKET_CASES(KIND_PROD2, PCLS_CASE)
@@ -852,6 +891,37 @@ __global__ void __launch_bounds__(1024) tile_kernel(ProblemDev P, TileArgs A) {
   extern __shared__ unsigned long long lds_raw[];
   A.r0 = blockIdx.x << A.logT;
   resident_tile<MAXB, AT>(P, A, lds_raw);
+}
+
+// ---------------------------------------------------- constraint statistics
+// One workgroup per restart evaluates every constraint once and adds, per
+// constraint, the sum over its literals of (dFE_c/dy_i)^2 (unweighted) into a
+// 64-bit fixed-point accumulator: exact integer sums, so the result does not
+// depend on the order in which restarts or waves arrive.
+template <int MAXB>
+__global__ void __launch_bounds__(1024) stats_kernel(ProblemDev P, const float* __restrict__ X, int ldx,
+                                                     StatsOut so) {
+  extern __shared__ unsigned long long lds_raw[];
+  float* xs = reinterpret_cast<float*>(lds_raw);
+  int* ctr = reinterpret_cast<int*>(xs + ((P.n + 1) & ~1));
+  const int r = blockIdx.x;
+  for (int i = threadIdx.x; i < P.n; i += blockDim.x) xs[i] = X[(size_t)i * ldx + r];
+  if ((int)threadIdx.x < P.n_segments) ctr[threadIdx.x] = 0;
+  __syncthreads();
+  ObjAcc facc{0, 0, 0};
+  kptr<Segment> segs = kconst(P.segments);
+  for (int sg = 0; sg < P.n_segments; ++sg) {
+    const Segment S{segs[sg].kind,    segs[sg].bucket, segs[sg].c_begin,   segs[sg].c_count,
+                    segs[sg].lit_base, segs[sg].k_fixed, segs[sg].cls_fixed, segs[sg].m_max};
+    run_any_segment<MAXB, unsigned int, true>(P, S, xs, nullptr, facc, 1.f, 0.f, (int)threadIdx.x, 0, ctr + sg, so);
+  }
+}
+
+// acc (planned order, scale 2^s) -> out[caller's constraint index]
+__global__ void stats_finish_kernel(const unsigned long long* __restrict__ acc, const int32_t* __restrict__ perm,
+                                    int m, double inv, float* __restrict__ out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < m) out[perm[i]] = (float)((double)(long long)acc[i] * inv);
 }
 
 // ------------------------------------------------------------ batched engine
@@ -1096,7 +1166,10 @@ int32_t device_limits(DeviceLimits& out) {
                               (const void*)tile_kernel<12, unsigned long long>,
                               (const void*)tile_kernel<7, unsigned int>,
                               (const void*)tile_kernel<9, unsigned int>,
-                              (const void*)tile_kernel<12, unsigned int>};
+                              (const void*)tile_kernel<12, unsigned int>,
+                              (const void*)stats_kernel<7>,
+                              (const void*)stats_kernel<9>,
+                              (const void*)stats_kernel<12>};
     for (const void* f : variants)
       PCLS_HIP(hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, d.lds_max), "hipFuncSetAttribute");
     d.lds_attr_set = true;
@@ -1484,6 +1557,7 @@ int32_t pcls_upload(pcls_problem* p, void* d_ws, size_t bytes, void* stream) {
   D.unit_weights = p->unit_weights;
   D.max_k = p->max_k;
   D.occ = (const int32_t*)(b + p->off_occ);
+  D.perm = (const int32_t*)(b + p->off_perm);
   p->d_ws = d_ws;
   p->ws_bytes = bytes;
   clear_error();
@@ -1569,6 +1643,39 @@ int32_t pcls_extract(const pcls_problem* p, int32_t R, const float* d_x, int8_t*
     hipLaunchKernelGGL(extract_best_kernel, dim3(1), dim3(1024), 0, s, d_unsat, R, d_best);
     PCLS_HIP(hipGetLastError(), "extract_best launch");
   }
+  clear_error();
+  return PCLS_OK;
+}
+
+int32_t pcls_constraint_grad_stats(const pcls_problem* p, int32_t R, const float* d_x, uint64_t* d_acc_u64,
+                                   float* d_out, void* stream) {
+  unsigned long long* d_acc = reinterpret_cast<unsigned long long*>(d_acc_u64);
+  int32_t st = check_bound(p);
+  if (st != PCLS_OK) return st;
+  if (R < 1) return set_error(PCLS_E_INVALID, "R must be >= 1");
+  if (p->m == 0) return PCLS_OK;
+  if (!d_x || !d_acc || !d_out) return set_error(PCLS_E_INVALID, "d_x, d_acc and d_out must not be NULL");
+  DeviceLimits lim;
+  st = device_limits(lim);
+  if (st != PCLS_OK) return st;
+  const size_t lds = (size_t)((p->n + 1) & ~1) * 4 + 4 * kMaxSegments;
+  if (lds > (size_t)lim.lds_max)
+    return set_error(PCLS_E_UNSUPPORTED, "state of %d variables does not fit in LDS", p->n);
+  // every term is at most 1, so a constraint's sum over R restarts is at most R k
+  const int bits = (int)std::ceil(std::log2((double)R * (double)std::max(1, p->max_k) + 1.0));
+  const int sc = std::min(40, 60 - bits);
+  hipStream_t s = (hipStream_t)stream;
+  hipLaunchKernelGGL(fill_u32_kernel, dim3((2 * p->m + 255) / 256), dim3(256), 0, s, (unsigned int*)d_acc, 0u,
+                     2 * p->m);
+  PCLS_HIP(hipGetLastError(), "fill launch");
+  StatsOut so{d_acc, std::ldexp(1.0f, sc)};
+  const int block = p->n > 4096 ? 1024 : 256;
+  auto kern = p->max_bucket <= 7 ? stats_kernel<7> : (p->max_bucket <= 9 ? stats_kernel<9> : stats_kernel<12>);
+  hipLaunchKernelGGL(kern, dim3(R), dim3(block), lds, s, p->dev, d_x, round_up64(R), so);
+  PCLS_HIP(hipGetLastError(), "stats_kernel launch");
+  hipLaunchKernelGGL(stats_finish_kernel, dim3((p->m + 255) / 256), dim3(256), 0, s, d_acc, p->dev.perm, p->m,
+                     std::ldexp(1.0, -sc), d_out);
+  PCLS_HIP(hipGetLastError(), "stats_finish launch");
   clear_error();
   return PCLS_OK;
 }

@@ -430,6 +430,7 @@ int32_t build_plan(int32_t n, int32_t m, const int32_t* row_ptr, const int32_t* 
   P->off_rowptr = place(sizeof(int32_t) * ((size_t)m + 1));
   P->off_lit = place(sizeof(int32_t) * (size_t)L);
   P->off_occ = place(sizeof(int32_t) * (size_t)n);
+  P->off_perm = place(sizeof(int32_t) * (size_t)m);
   size_t total = align_up(std::max<size_t>(off, 256), 256);
   P->image.assign(total, 0);
   auto put = [&](size_t at, const void* src, size_t bytes) {
@@ -446,6 +447,7 @@ int32_t build_plan(int32_t n, int32_t m, const int32_t* row_ptr, const int32_t* 
   put(P->off_rowptr, P->row_ptr.data(), sizeof(int32_t) * ((size_t)m + 1));
   put(P->off_lit, P->lit.data(), sizeof(int32_t) * (size_t)L);
   put(P->off_occ, P->occ.data(), sizeof(int32_t) * (size_t)n);
+  put(P->off_perm, P->perm.data(), sizeof(int32_t) * (size_t)m);
 
   *out = P;
   *workspace_bytes = total;

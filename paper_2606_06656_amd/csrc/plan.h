@@ -39,7 +39,7 @@ struct pcls_problem {
   // device image
   std::vector<uint8_t> image;
   size_t off_segments = 0, off_classes = 0, off_nodes = 0, off_sp = 0, off_litT = 0, off_ck = 0,
-         off_ccls = 0, off_cw = 0, off_rowptr = 0, off_lit = 0, off_occ = 0;
+         off_ccls = 0, off_cw = 0, off_rowptr = 0, off_lit = 0, off_occ = 0, off_perm = 0;
   void* d_ws = nullptr;
   size_t ws_bytes = 0;
   pcls::ProblemDev dev{};

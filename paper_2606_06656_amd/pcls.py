@@ -26,7 +26,7 @@ EXPORTS = ["pcls_plan", "pcls_plan_ex", "pcls_problem_info", "pcls_upload", "pcl
            "pcls_destroy", "pcls_last_error",
            "pcls_batch_create", "pcls_batch_bind", "pcls_batch_set_config", "pcls_batch_get_config",
            "pcls_batch_step", "pcls_batch_capture", "pcls_batch_replay", "pcls_batch_autotune",
-           "pcls_batch_destroy", "pcls_valu_probe"]
+           "pcls_batch_destroy", "pcls_valu_probe", "pcls_constraint_grad_stats"]
 
 
 class PclsError(RuntimeError):
@@ -100,6 +100,8 @@ def load_library():
     L.pcls_last_error.argtypes = []
     L.pcls_valu_probe.restype = i32
     L.pcls_valu_probe.argtypes = [i32, i32, vp, vp]
+    L.pcls_constraint_grad_stats.restype = i32
+    L.pcls_constraint_grad_stats.argtypes = [P, i32, vp, vp, vp, vp]
     _lib = L
     return L
 
@@ -271,6 +273,18 @@ class Problem(Plan):
         check(load_library().pcls_step_ex(self.handle, int(R), _tptr(X), float(lr), int(n_steps), _tptr(tr),
                                           ctypes.byref(opt), _stream()))
         return tr, it
+
+    def constraint_grad_stats(self, X, R: int):
+        """Per constraint (caller's order): sum over the R restarts of the squared
+        unweighted gradient with respect to the constraint's literal values."""
+        import torch
+        self._check_state(X, R)
+        m = self.info().n_cons
+        acc = torch.empty(max(m, 1), dtype=torch.int64, device=self.device)
+        out = torch.zeros(m, dtype=torch.float32, device=self.device)
+        check(load_library().pcls_constraint_grad_stats(self.handle, int(R), _tptr(X), _tptr(acc), _tptr(out),
+                                                        _stream()))
+        return out
 
     def extract(self, X, R: int, want_assign: bool = True):
         import torch

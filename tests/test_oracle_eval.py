@@ -347,3 +347,28 @@ def test_init_uniform_range_and_dyadic():
     # counter mapping: x[r][v] from counter (r, v, 0, 0), key (seed lo, seed hi)
     o = N.philox4x32_10([3, 7, 0, 0], [123, 0])
     assert x[3, 7] == ((int(o[0]) >> 8) - 2 ** 23) / 2 ** 23
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_constraint_grad_sq_brute_force(seed):
+    """orc_constraint_grad_sq: per constraint, the sum over rows of the squared
+    literal gradient, where each partial derivative is the exact multilinear
+    difference (FE(y_i = 1) - FE(y_i = -1)) / 2 of the exact expectation."""
+    rng = np.random.default_rng(seed)
+    inst = synth.mixed_small(n=9, seed=seed, kmax=6, count=8)
+    op = N.OracleProblem(inst.n, inst.row_ptr, inst.lit, inst.ctype, inst.param, inst.weight)
+    R = 3
+    x = rng.integers(-64, 65, (R, inst.n)) / 64.0  # dyadic points, exact in the rationals
+    got = op.constraint_grad_sq(x)
+    for c in range(inst.m):
+        b, e = inst.row_ptr[c], inst.row_ptr[c + 1]
+        k = e - b
+        sp = C.spectrum(int(inst.ctype[c]), k, int(inst.param[c]))
+        want = Fraction(0)
+        for r in range(R):
+            y = [float(np.sign(inst.lit[i]) * x[r, abs(inst.lit[i]) - 1]) for i in range(b, e)]
+            for i in range(k):
+                hi = exact_expectation(sp, y[:i] + [1.0] + y[i + 1:])
+                lo = exact_expectation(sp, y[:i] + [-1.0] + y[i + 1:])
+                want += ((hi - lo) / 2) ** 2
+        assert got[c] == pytest.approx(float(want), rel=1e-12, abs=1e-14), c
