@@ -364,16 +364,16 @@ __device__ __forceinline__ void dft_pair(const ProblemDev& P, int m_max, int cls
       const cf xq = grp_suffix_c<G>(run, lig, T);
       const cf tot = cmul(run, xq);
       fe = fmaf(N.wr, tot.r, fmaf(-N.wi, tot.i, fe));
-      // gradient weight with the group prefix folded in
-      const cf gw = cmul(cf{N.gr, N.gi}, xp);
-      cf suf = xq;
+      // The gradient of literal j is Re(gw * prefix_j * suffix_j), gw the node's
+      // gradient weight: carrying S_j = gw * (group prefix) * suffix_j down the
+      // literals leaves one real part of a product per literal.
+      cf S = cmul(cmul(cf{N.gr, N.gi}, xp), xq);
 #pragma unroll
       for (int j = J - 1; j >= 0; --j) {
-        const cf pz = cmul(pre[j], suf);
-        g[j] = fmaf(gw.r, pz.r, fmaf(-gw.i, pz.i, g[j]));  // Re(gw * pz)
+        g[j] = fmaf(pre[j].r, S.r, fmaf(-pre[j].i, S.i, g[j]));  // Re(pre_j * S_j)
         const bool ok = kExact || fp.code[j] != -1;
         const cf f = ok ? cf{fmaf(N.br, y[j], N.ar), fmaf(N.bi, y[j], N.ai)} : cf{1.f, 0.f};
-        suf = cmul(suf, f);
+        S = cmul(S, f);
       }
     }
   }
