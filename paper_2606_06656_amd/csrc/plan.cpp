@@ -55,6 +55,72 @@ struct ClassKey {
 // and sum_t (-1)^t Pr[T = t] = prod y_i.
 static int pmf_window(const std::vector<int>& sp, float* d, float* h);
 
+// LDS bank-aware order of one run of short constraints (one lane per pair).
+// A wave instruction reads slot j of a block of consecutive constraints; with T
+// restarts per tile the rows of its variables occupy bank groups v mod (64/T')
+// for blocks of 64/T' constraints (T' = T, or T/2 with two restarts per lane),
+// and variables in the same group serialise.  For each position (relative to
+// the segment start, so blocks align with the kernel's chunks) the greedy picks,
+// among the next 16 constraints of the run and their cyclic slot rotations,
+// the one adding the fewest same-group pairs over the (block, groups) layouts
+// (64, 64), (64, 32), (32, 16) and (16, 8).  Symmetric constraints do not depend
+// on their literal order, so rotating the slots changes no value.
+static void bank_aware_order(const int32_t* row_ptr, const int32_t* lit, int k, int32_t* run, int len, int seg_off,
+                             std::vector<uint8_t>& rot_of) {
+  constexpr int kWindow = 16, kCfg = 4;
+  const int blk[kCfg] = {64, 64, 32, 16}, mask[kCfg] = {63, 31, 15, 7};
+  uint16_t occ[kCfg][8][64];
+  struct Cand {
+    int32_t c;
+    uint8_t res[8];  // variable mod 64 per slot
+  };
+  auto make = [&](int32_t c) {
+    Cand d{c, {}};
+    for (int i = 0; i < k; ++i) {
+      const int l = lit[row_ptr[c] + i];
+      d.res[i] = (uint8_t)(((l > 0 ? l : -l) - 1) & 63);
+    }
+    return d;
+  };
+  // window: the first kWindow not-yet-placed constraints of the run, in run order
+  Cand win[kWindow];
+  int nwin = 0, next = 0;
+  while (nwin < kWindow && next < len) win[nwin++] = make(run[next++]);
+  std::vector<int32_t> out;
+  out.reserve(len);
+  for (int q = 0; q < len; ++q) {
+    const int pos = seg_off + q;
+    for (int c = 0; c < kCfg; ++c)
+      if (pos % blk[c] == 0) std::memset(occ[c], 0, sizeof occ[c]);
+    int best = 0, best_rot = 0, best_cost = 1 << 30;
+    for (int w = 0; w < nwin && best_cost > 0; ++w) {
+      for (int r = 0; r < k && best_cost > 0; ++r) {
+        int cost = 0;
+        for (int j = 0; j < k; ++j) {
+          const int v = win[w].res[(j + r) % k];
+          for (int c = 0; c < kCfg; ++c) cost += occ[c][j][v & mask[c]];
+        }
+        if (cost < best_cost) {
+          best_cost = cost;
+          best = w;
+          best_rot = r;
+        }
+      }
+    }
+    const Cand chosen = win[best];
+    for (int j = 0; j < k; ++j) {
+      const int v = chosen.res[(j + best_rot) % k];
+      for (int c = 0; c < kCfg; ++c) ++occ[c][j][v & mask[c]];
+    }
+    rot_of[(size_t)chosen.c] = (uint8_t)best_rot;
+    out.push_back(chosen.c);
+    for (int w = best; w + 1 < nwin; ++w) win[w] = win[w + 1];  // keep run order
+    --nwin;
+    if (next < len) win[nwin++] = make(run[next++]);
+  }
+  std::copy(out.begin(), out.end(), run);
+}
+
 static void classify(const std::vector<int>& sp, bool force_generic, ClassRec& C) {
   const int k = (int)sp.size() - 1;
   bool all_eq = true, tail_eq = true, head_eq = true, alt = true, mid_eq = true;
@@ -334,6 +400,25 @@ int32_t build_plan(int32_t n, int32_t m, const int32_t* row_ptr, const int32_t* 
     return std::make_tuple(kind, b, cls_orig[c], c);
   };
   std::sort(order.begin(), order.end(), [&](int a, int b) { return seg_key(a) < seg_key(b); });
+  // bank-aware order inside each class run of the short buckets (one lane per pair)
+  std::vector<uint8_t> rot_of((size_t)m, 0);
+  {
+    int seg_start = 0;
+    for (int a = 0; a < m;) {
+      const ClassRec& C = P->classes[cls_orig[order[a]]];
+      if (C.kind == KIND_CONST) break;
+      const int b = bucket_of(C.k);
+      if (a > 0) {
+        const ClassRec& Cp = P->classes[cls_orig[order[a - 1]]];
+        if (Cp.kind != C.kind || bucket_of(Cp.k) != b) seg_start = a;
+      }
+      int e = a;
+      while (e < m && cls_orig[order[e]] == cls_orig[order[a]]) ++e;
+      if (kBucketKmax[b] <= 8 && group_size(C.kind, kBucketKmax[b]) == 1)
+        bank_aware_order(row_ptr, lit, C.k, order.data() + a, e - a, a - seg_start, rot_of);
+      a = e;
+    }
+  }
   P->perm = order;
   P->c_k.resize(m);
   P->c_cls.resize(m);
@@ -349,7 +434,7 @@ int32_t build_plan(int32_t n, int32_t m, const int32_t* row_ptr, const int32_t* 
     P->c_w[j] = weight ? weight[c] : 1.0f;
     P->row_ptr[j + 1] = P->row_ptr[j] + k;
     for (int i = 0; i < k; ++i) {
-      int l = lit[row_ptr[c] + i];
+      int l = lit[row_ptr[c] + (i + rot_of[(size_t)c]) % k];
       int v = (l > 0 ? l : -l) - 1;
       P->lit[P->row_ptr[j] + i] = (v << 1) | (l < 0 ? 1 : 0);
     }
