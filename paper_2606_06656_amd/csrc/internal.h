@@ -30,16 +30,26 @@ constexpr int kPmfMaxK = 8;    // longest constraint of the PMF kind (one lane p
 
 // Length buckets of the segment kernels: literals per constraint padded to KMAX,
 // processed by groups of G lanes holding J = KMAX / G literals each.
-constexpr int kNumBuckets = 13;
-constexpr int kBucketKmax[kNumBuckets] = {1, 2, 3, 4, 5, 6, 7, 8, 16, 32, 64, 128, 256};
+constexpr int kNumBuckets = 18;
+constexpr int kBucketKmax[kNumBuckets] = {1, 2, 3, 4, 5, 6, 7, 8, 12, 16, 24, 32, 48, 64, 96, 128, 192, 256};
+// Kernel variants, by the longest bucket they are compiled for.
+constexpr int kMaxbShort = 7;                // k <= 8
+constexpr int kMaxbMid = 11;                 // k <= 32
+constexpr int kMaxbAll = kNumBuckets - 1;    // k <= 256
 constexpr int kMaxK = 256;
 constexpr int kMaxSegments = 4 * kNumBuckets;  // (kind, bucket) pairs of the non-constant kinds
 
 // Lanes per (constraint, restart) pair: one lane holds up to 16 literals of a
 // product kind or 8 of the DFT kind (register budget at 4 waves per SIMD);
-// longer constraints spread over G lanes of 8 literals each.
+// longer constraints spread over G lanes (a power of two) of at most 8 literals
+// each (6 for the buckets 12, 24, ..., 192).
+constexpr int lane_groups(int kmax) {
+  int g = 1;
+  while (kmax > 8 * g) g *= 2;
+  return g;
+}
 constexpr int group_size(int kind, int kmax) {
-  return kind == KIND_PMF ? 1 : kind == KIND_DFT ? (kmax <= 8 ? 1 : kmax / 8) : (kmax <= 16 ? 1 : kmax / 8);
+  return kind == KIND_PMF ? 1 : (kmax <= 8 || (kind != KIND_DFT && kmax <= 16)) ? 1 : lane_groups(kmax);
 }
 
 inline int bucket_of(int k) {

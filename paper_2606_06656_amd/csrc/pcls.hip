@@ -524,7 +524,7 @@ __device__ __forceinline__ void prod_pair_r2(const Fetched<KMAX>& fp, int t2, in
 // pair per lane: their register budget goes to the long groups.
 template <int KIND, int J, int MAXB>
 constexpr int pairs_per_lane() {
-  return (KIND == KIND_DFT || KIND == KIND_PMF || MAXB > 7) ? 1 : (J <= 4 ? 4 : (J <= 8 ? 2 : 1));
+  return (KIND == KIND_DFT || KIND == KIND_PMF || MAXB > kMaxbShort) ? 1 : (J <= 4 ? 4 : (J <= 8 ? 2 : 1));
 }
 
 template <int J, int U>
@@ -595,7 +595,7 @@ template <int KIND, int KMAX, int MAXB, class AT, bool ST = false>
 __device__ __forceinline__ void run_segment(const ProblemDev& P, const Segment& S, const float* xs, AT* gs,
                                             ObjAcc& facc, float gsc, float fsc, int tid, int logT, int* ctr,
                                             StatsOut so = {}) {
-  if constexpr (!ST && (KIND == KIND_PROD1 || KIND == KIND_PROD2) && MAXB <= 7 && KMAX <= 8) {
+  if constexpr (!ST && (KIND == KIND_PROD1 || KIND == KIND_PROD2) && MAXB <= kMaxbShort && KMAX <= 8) {
     if (logT >= 1) {
       run_segment_r2<KIND, KMAX>(P, S, xs, gs, facc, gsc, fsc, tid, logT, ctr);
       return;
@@ -701,11 +701,16 @@ __device__ __forceinline__ void run_segment(const ProblemDev& P, const Segment& 
   X(KIND, 5, 6)                    \
   X(KIND, 6, 7)                    \
   X(KIND, 7, 8)                    \
-  X(KIND, 8, 16)                   \
-  X(KIND, 9, 32)                   \
-  X(KIND, 10, 64)                  \
-  X(KIND, 11, 128)                 \
-  X(KIND, 12, 256)
+  X(KIND, 8, 12)                   \
+  X(KIND, 9, 16)                   \
+  X(KIND, 10, 24)                  \
+  X(KIND, 11, 32)                  \
+  X(KIND, 12, 48)                  \
+  X(KIND, 13, 64)                  \
+  X(KIND, 14, 96)                  \
+  X(KIND, 15, 128)                 \
+  X(KIND, 16, 192)                 \
+  X(KIND, 17, 256)
 
 #define PCLS_SHORT_BUCKET_CASES(KIND, X) \
   X(KIND, 0, 1)                          \
@@ -800,7 +805,7 @@ __device__ __forceinline__ void resident_tile(const ProblemDev& P, const TileArg
     // lanes with equal (lane mod T) hold the same restart; integer sums are exact
     for (int o = T; o < kWave; o <<= 1) facc.own += __shfl_xor(facc.own, o);
     if ((tid & (kWave - 1)) < T) atomicAdd(&Fs[t], (unsigned long long)facc.own);
-    if constexpr (MAXB <= 7) {
+    if constexpr (MAXB <= kMaxbShort) {
       if (logT >= 1) {  // two-restart lanes: restarts 2 t2 and 2 t2 + 1, t2 = lane mod T/2
         for (int o = T >> 1; o < kWave; o <<= 1) {
           facc.even += __shfl_xor(facc.even, o);
@@ -1161,15 +1166,15 @@ int32_t device_limits(DeviceLimits& out) {
     d.n_cu = v;
   }
   if (!d.lds_attr_set) {
-    const void* variants[] = {(const void*)tile_kernel<7, unsigned long long>,
-                              (const void*)tile_kernel<9, unsigned long long>,
-                              (const void*)tile_kernel<12, unsigned long long>,
-                              (const void*)tile_kernel<7, unsigned int>,
-                              (const void*)tile_kernel<9, unsigned int>,
-                              (const void*)tile_kernel<12, unsigned int>,
-                              (const void*)stats_kernel<7>,
-                              (const void*)stats_kernel<9>,
-                              (const void*)stats_kernel<12>};
+    const void* variants[] = {(const void*)tile_kernel<kMaxbShort, unsigned long long>,
+                              (const void*)tile_kernel<kMaxbMid, unsigned long long>,
+                              (const void*)tile_kernel<kMaxbAll, unsigned long long>,
+                              (const void*)tile_kernel<kMaxbShort, unsigned int>,
+                              (const void*)tile_kernel<kMaxbMid, unsigned int>,
+                              (const void*)tile_kernel<kMaxbAll, unsigned int>,
+                              (const void*)stats_kernel<kMaxbShort>,
+                              (const void*)stats_kernel<kMaxbMid>,
+                              (const void*)stats_kernel<kMaxbAll>};
     for (const void* f : variants)
       PCLS_HIP(hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, d.lds_max), "hipFuncSetAttribute");
     d.lds_attr_set = true;
@@ -1286,13 +1291,13 @@ int32_t launch_tile(const pcls_problem* p, int R, float* d_x, float lr, int n_st
   A.tol = opt ? opt->tol : 0.f;
   A.iters = opt ? opt->d_iters : nullptr;
   if (L.acc64) {
-    auto kern = p->max_bucket <= 7 ? tile_kernel<7, unsigned long long>
-                                   : (p->max_bucket <= 9 ? tile_kernel<9, unsigned long long>
-                                                         : tile_kernel<12, unsigned long long>);
+    auto kern = p->max_bucket <= kMaxbShort ? tile_kernel<kMaxbShort, unsigned long long>
+                                   : (p->max_bucket <= kMaxbMid ? tile_kernel<kMaxbMid, unsigned long long>
+                                                         : tile_kernel<kMaxbAll, unsigned long long>);
     hipLaunchKernelGGL(kern, dim3(tiles), dim3(L.block), L.lds, stream, p->dev, A);
   } else {
-    auto kern = p->max_bucket <= 7 ? tile_kernel<7, unsigned int>
-                                   : (p->max_bucket <= 9 ? tile_kernel<9, unsigned int> : tile_kernel<12, unsigned int>);
+    auto kern = p->max_bucket <= kMaxbShort ? tile_kernel<kMaxbShort, unsigned int>
+                                   : (p->max_bucket <= kMaxbMid ? tile_kernel<kMaxbMid, unsigned int> : tile_kernel<kMaxbAll, unsigned int>);
     hipLaunchKernelGGL(kern, dim3(tiles), dim3(L.block), L.lds, stream, p->dev, A);
   }
   PCLS_HIP(hipGetLastError(), "tile_kernel launch");
@@ -1449,12 +1454,12 @@ int32_t batch_launch(BatchState& b, float lr, int n_steps, hipStream_t stream) {
   PCLS_HIP(hipGetLastError(), "fill launch");
   const dim3 grid(b.grid), block(b.cfg.block_threads);
   if (b.acc64) {
-    auto k = b.maxb <= 7 ? batch_kernel<7, unsigned long long>
-                         : (b.maxb <= 9 ? batch_kernel<9, unsigned long long> : batch_kernel<12, unsigned long long>);
+    auto k = b.maxb <= kMaxbShort ? batch_kernel<kMaxbShort, unsigned long long>
+                         : (b.maxb <= kMaxbMid ? batch_kernel<kMaxbMid, unsigned long long> : batch_kernel<kMaxbAll, unsigned long long>);
     hipLaunchKernelGGL(k, grid, block, b.lds, stream, insts, items, b.n_items, counter, lr, n_steps);
   } else {
-    auto k = b.maxb <= 7 ? batch_kernel<7, unsigned int>
-                         : (b.maxb <= 9 ? batch_kernel<9, unsigned int> : batch_kernel<12, unsigned int>);
+    auto k = b.maxb <= kMaxbShort ? batch_kernel<kMaxbShort, unsigned int>
+                         : (b.maxb <= kMaxbMid ? batch_kernel<kMaxbMid, unsigned int> : batch_kernel<kMaxbAll, unsigned int>);
     hipLaunchKernelGGL(k, grid, block, b.lds, stream, insts, items, b.n_items, counter, lr, n_steps);
   }
   PCLS_HIP(hipGetLastError(), "batch_kernel launch");
@@ -1472,9 +1477,9 @@ int32_t batch_attrs() {
   if (st != PCLS_OK) return st;
   std::lock_guard<std::mutex> lk(g_batch_attr_mu);
   if (dev >= 0 && dev < 64 && !g_batch_attr_set[dev]) {
-    const void* fs[] = {(const void*)batch_kernel<7, unsigned long long>, (const void*)batch_kernel<9, unsigned long long>,
-                        (const void*)batch_kernel<12, unsigned long long>, (const void*)batch_kernel<7, unsigned int>,
-                        (const void*)batch_kernel<9, unsigned int>, (const void*)batch_kernel<12, unsigned int>};
+    const void* fs[] = {(const void*)batch_kernel<kMaxbShort, unsigned long long>, (const void*)batch_kernel<kMaxbMid, unsigned long long>,
+                        (const void*)batch_kernel<kMaxbAll, unsigned long long>, (const void*)batch_kernel<kMaxbShort, unsigned int>,
+                        (const void*)batch_kernel<kMaxbMid, unsigned int>, (const void*)batch_kernel<kMaxbAll, unsigned int>};
     // the kernel's static LDS word sits beside the dynamic tiles
     for (const void* f : fs)
       PCLS_HIP(hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, lim.lds_max - 256),
@@ -1670,7 +1675,7 @@ int32_t pcls_constraint_grad_stats(const pcls_problem* p, int32_t R, const float
   PCLS_HIP(hipGetLastError(), "fill launch");
   StatsOut so{d_acc, std::ldexp(1.0f, sc)};
   const int block = p->n > 4096 ? 1024 : 256;
-  auto kern = p->max_bucket <= 7 ? stats_kernel<7> : (p->max_bucket <= 9 ? stats_kernel<9> : stats_kernel<12>);
+  auto kern = p->max_bucket <= kMaxbShort ? stats_kernel<kMaxbShort> : (p->max_bucket <= kMaxbMid ? stats_kernel<kMaxbMid> : stats_kernel<kMaxbAll>);
   hipLaunchKernelGGL(kern, dim3(R), dim3(block), lds, s, p->dev, d_x, round_up64(R), so);
   PCLS_HIP(hipGetLastError(), "stats_kernel launch");
   hipLaunchKernelGGL(stats_finish_kernel, dim3((p->m + 255) / 256), dim3(256), 0, s, d_acc, p->dev.perm, p->m,

@@ -131,7 +131,7 @@ def test_plan_segments_by_kind():
     p = pcls.Plan.from_instance(inst)
     info = p.info()
     assert info.n_cons == inst.m and info.n_lits == inst.L
-    assert 1 <= info.n_segments <= 4 * 13
+    assert 1 <= info.n_segments <= 4 * 18
 
 
 def _expected_kind(sp):

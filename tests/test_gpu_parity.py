@@ -22,7 +22,8 @@ from gpu_util import TOL, assert_obj_grad, corner_mix, log, oracle_for, quantum_
 
 DEV = "cuda"
 
-K_LIST = [1, 2, 3, 4, 5, 6, 7, 8, 9, 12, 15, 16, 17, 24, 31, 32, 33, 48, 63, 64, 65, 96, 127, 128, 129, 192,
+K_LIST = [1, 2, 3, 4, 5, 6, 7, 8, 9, 12, 13, 15, 16, 17, 24, 25, 31, 32, 33, 48, 49, 63, 64, 65, 96, 97, 127, 128, 129,
+          160, 192, 193,
           255, 256]
 
 
