@@ -92,6 +92,9 @@ def roofline(kernel: str, key: str, alg_bytes_per_launch: float, launch_ms: floa
            "frac": achieved / HBM_PEAK_GBS, "traffic": None if tr is None else tr["hbm_bytes_per_launch"],
            "kernel": kernel, "launch_ms": launch_ms, "steps_per_launch": steps_per_launch,
            "model": "gather model: 8 B per literal-eval + 8 B per (variable, restart) + CSR per step"}
+    if tr is not None:
+        # HBM rate the counters measured: the state stays in LDS, so it is far below achieved
+        out["traffic_gbs"] = tr["hbm_bytes_per_launch"] / (launch_ms / 1e3) / 1e9
     ct = profile_record(kernel, key, "counters", steps_per_launch)
     if ct is not None:
         from paper_2606_06656_amd import pcls
