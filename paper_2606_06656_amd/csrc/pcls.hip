@@ -837,6 +837,22 @@ __device__ __forceinline__ void resident_tile(const ProblemDev& P, const TileArg
           A.g_out[(size_t)v * ldx + r0 + tt] = FixedAcc<AT>::value(gs[i], A.ginv, P.occ[v]);
         }
       }
+    } else if (sizeof(AT) == 4 && A.tol <= 0.f && !A.fixed && (NT & 3) == 0) {
+      // plain step, 32-bit accumulator: four elements per 16-byte LDS access
+      // (same arithmetic per element as the general loop below)
+      const float lr = A.lr, ginv = A.ginv;
+      float4* x4 = reinterpret_cast<float4*>(xs);
+      uint4* g4 = reinterpret_cast<uint4*>(gs);
+      for (int i = tid; i < (NT >> 2); i += nth) {
+        float4 x = x4[i];
+        const uint4 g = g4[i];
+        x.x = fminf(1.f, fmaxf(-1.f, fmaf(-lr, (float)(int)g.x * ginv, x.x)));
+        x.y = fminf(1.f, fmaxf(-1.f, fmaf(-lr, (float)(int)g.y * ginv, x.y)));
+        x.z = fminf(1.f, fmaxf(-1.f, fmaf(-lr, (float)(int)g.z * ginv, x.z)));
+        x.w = fminf(1.f, fmaxf(-1.f, fmaf(-lr, (float)(int)g.w * ginv, x.w)));
+        x4[i] = x;
+        g4[i] = make_uint4(0u, 0u, 0u, 0u);
+      }
     } else {
       const float lr = A.lr;
       float dmax = 0.f;  // this thread's elements all belong to restart t (nth is a multiple of T)
@@ -893,7 +909,7 @@ __device__ __forceinline__ void resident_tile(const ProblemDev& P, const TileArg
 // fixed-point gradient accumulator (64-bit, or 32-bit where LDS is short).
 template <int MAXB, class AT>
 __global__ void __launch_bounds__(1024) tile_kernel(ProblemDev P, TileArgs A) {
-  extern __shared__ unsigned long long lds_raw[];
+  extern __shared__ __attribute__((aligned(16))) unsigned long long lds_raw[];  // 16 B: vector LDS accesses
   A.r0 = blockIdx.x << A.logT;
   resident_tile<MAXB, AT>(P, A, lds_raw);
 }
@@ -906,7 +922,7 @@ __global__ void __launch_bounds__(1024) tile_kernel(ProblemDev P, TileArgs A) {
 template <int MAXB>
 __global__ void __launch_bounds__(1024) stats_kernel(ProblemDev P, const float* __restrict__ X, int ldx,
                                                      StatsOut so) {
-  extern __shared__ unsigned long long lds_raw[];
+  extern __shared__ __attribute__((aligned(16))) unsigned long long lds_raw[];  // 16 B: vector LDS accesses
   float* xs = reinterpret_cast<float*>(lds_raw);
   int* ctr = reinterpret_cast<int*>(xs + ((P.n + 1) & ~1));
   const int r = blockIdx.x;
@@ -974,7 +990,7 @@ template <int MAXB, class AT>
 __global__ void __launch_bounds__(1024) batch_kernel(const BatchInst* __restrict__ insts,
                                                      const BatchItem* __restrict__ items, int n_items,
                                                      unsigned int* __restrict__ counter, float lr, int n_steps) {
-  extern __shared__ unsigned long long lds_raw[];
+  extern __shared__ __attribute__((aligned(16))) unsigned long long lds_raw[];  // 16 B: vector LDS accesses
   __shared__ int claimed;
   for (;;) {
     if (threadIdx.x == 0) claimed = (int)atomicAdd(counter, 1u);
