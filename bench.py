@@ -145,9 +145,11 @@ def bench_batch(args, insts, R, lr, key):
         X = p.new_state(R)
         p.init_restarts(X, R, 4000 + k)
         states.append(X)
-    b = Batch(probs, [R] * len(probs), states)
-    tune = b.autotune(lr, probe_steps=3, cache_path=args.tune_cache)
     S = args.graph_steps
+    # every step writes each restart's objective (obj + grad per step)
+    traces = [torch.empty((S, R), dtype=torch.float32, device="cuda:0") for _ in probs]
+    b = Batch(probs, [R] * len(probs), states, traces)
+    tune = b.autotune(lr, probe_steps=3, cache_path=args.tune_cache)
     reps = max(1, args.steps // S)
     steps = reps * S
     b.capture(lr, S)
@@ -272,20 +274,23 @@ def main():
     S = max(1, min(args.steps_per_launch, args.steps))
     n_launch = max(1, args.steps // S)
     steps = n_launch * S
+    # every step writes each restart's objective at its iterate (obj + grad per step)
+    trace = torch.empty((S, R), dtype=torch.float32, device="cuda:0")
     for _ in range((args.warmup + S - 1) // S):
-        prob.step(X, R, lr, S)
+        prob.step(X, R, lr, S, trace=trace)
     torch.cuda.synchronize()
 
     start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     start.record(stream)
     for _ in range(n_launch):
-        prob.step(X, R, lr, S)  # one launch of the resident kernel runs S steps
+        prob.step(X, R, lr, S, trace=trace)  # one launch of the resident kernel runs S steps
     end.record(stream)
     torch.cuda.synchronize()
     ms = start.elapsed_time(end)
     t = ms / 1e3
 
     value = R * inst.L * steps / t
+    last_obj = trace[-1]
     out = {
         "metric": METRIC,
         "value": value,
@@ -301,6 +306,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": key, "n": inst.n, "m": inst.m, "L": inst.L, "restarts": R, "lr": lr,
                    "launch": prob.launch_info(R)},
+        "objective_last_step": {"min": float(last_obj.min()), "mean": float(last_obj.mean())},
         "roofline": roofline("tile_kernel", key, algorithmic_bytes_per_step(inst.n, inst.m, inst.L, R) * S,
                              ms / n_launch, S),
     }

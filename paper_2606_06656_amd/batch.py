@@ -89,6 +89,11 @@ class Batch:
         for p, r, X in zip(self.problems, self.restarts, states):
             p._check_state(X, r)
         xs = (ctypes.c_void_p * n)(*[X.data_ptr() for X in states])
+        if traces is not None:
+            for i, (t, r) in enumerate(zip(traces, self.restarts)):
+                if t is not None and (t.dtype.itemsize != 4 or t.dim() != 2 or t.shape[1] != r
+                                      or t.device != states[i].device):
+                    raise pcls.PclsError(pcls.PCLS_E_INVALID, f"trace {i} must be float32 [steps][{r}] on the device")
         tr = None if traces is None else (ctypes.c_void_p * n)(*[0 if t is None else t.data_ptr() for t in traces])
         pcls.check(L.pcls_batch_bind(self.handle, ctypes.c_void_p(self._ws), self.workspace_bytes, xs, tr,
                                      pcls._stream()))
@@ -107,10 +112,23 @@ class Batch:
         c = BatchConfig(block_threads, lds_budget, wgs_per_cu, accumulator_bits)
         pcls.check(_lib().pcls_batch_set_config(self.handle, ctypes.byref(c), pcls._stream()))
 
+    def _check_traces(self, n_steps: int):
+        """Bound traces receive n_steps rows per step call: refuse shorter ones."""
+        if self.traces is None:
+            return
+        for i, (t, r) in enumerate(zip(self.traces, self.restarts)):
+            if t is None:
+                continue
+            if t.dim() != 2 or t.shape[0] < n_steps or t.shape[1] != r or not t.is_contiguous():
+                raise pcls.PclsError(pcls.PCLS_E_INVALID,
+                                     f"trace {i} must be a contiguous [>= {n_steps}][{r}] tensor, got {tuple(t.shape)}")
+
     def step(self, lr: float, n_steps: int):
+        self._check_traces(n_steps)
         pcls.check(_lib().pcls_batch_step(self.handle, float(lr), int(n_steps), pcls._stream()))
 
     def capture(self, lr: float, n_steps: int):
+        self._check_traces(n_steps)
         pcls.check(_lib().pcls_batch_capture(self.handle, float(lr), int(n_steps), pcls._stream()))
 
     def replay(self):

@@ -249,10 +249,18 @@ class Problem(Plan):
         check(load_library().pcls_evaluate(self.handle, int(R), _tptr(X), _tptr(obj), _tptr(grad), _stream()))
         return obj, grad
 
-    def step(self, X, R: int, lr: float, n_steps: int = 1, trace: bool = False):
+    def step(self, X, R: int, lr: float, n_steps: int = 1, trace=False):
+        """n_steps projected-gradient steps; trace=True returns a new [n_steps][R]
+        objective trace, a float32 device tensor of that shape is written in place."""
         import torch
         self._check_state(X, R)
-        tr = torch.empty((n_steps, R), dtype=torch.float32, device=self.device) if trace else None
+        if isinstance(trace, torch.Tensor):
+            if trace.dtype != torch.float32 or tuple(trace.shape) != (n_steps, R) or trace.device != self.device \
+                    or not trace.is_contiguous():
+                raise PclsError(PCLS_E_INVALID, "trace must be a contiguous float32 [n_steps][R] device tensor")
+            tr = trace
+        else:
+            tr = torch.empty((n_steps, R), dtype=torch.float32, device=self.device) if trace else None
         check(load_library().pcls_step(self.handle, int(R), _tptr(X), float(lr), int(n_steps), _tptr(tr),
                                        _stream()))
         return tr

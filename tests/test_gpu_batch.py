@@ -152,3 +152,16 @@ def test_batch_errors():
         b.replay()  # nothing captured
     with pytest.raises(pcls.PclsError):
         Batch(probs, [4, 0])
+
+
+def test_short_traces_are_refused():
+    """A bound trace receives n_steps rows per step: asking for more steps than
+    it holds is refused before anything is launched."""
+    insts, probs, Rs, states = setup(2, 13, [8, 8])
+    traces = [torch.zeros((3, R), device=X.device) for R, X in zip(Rs, states)]
+    b = Batch(probs, Rs, states, traces)
+    b.step(0.1, 3)
+    with pytest.raises(pcls.PclsError):
+        b.step(0.1, 4)
+    with pytest.raises(pcls.PclsError):
+        b.capture(0.1, 5)
