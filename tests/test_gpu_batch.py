@@ -15,7 +15,7 @@ torch = pytest.importorskip("torch")
 
 from paper_2606_06656_amd import pcls, synth  # noqa: E402
 from paper_2606_06656_amd.batch import Batch  # noqa: E402
-from gpu_util import log, oracle_for, rows_of  # noqa: E402
+from gpu_util import TOL, assert_obj_grad, log, oracle_for, range_scales, rows_of  # noqa: E402
 from oracle import native as N  # noqa: E402
 
 
@@ -165,3 +165,35 @@ def test_short_traces_are_refused():
         b.step(0.1, 4)
     with pytest.raises(pcls.PclsError):
         b.capture(0.1, 5)
+
+
+def test_c4_full_size_sampled():
+    """256 uneven instances (n log-uniform on [100, 1e4], 64 restarts each) in one
+    batched launch with the autotuned configuration, as bench.py times it: the
+    objective of the first step and the first projected step of sampled
+    (instance, restart) pairs against the oracle."""
+    insts = synth.c4_batch(256)
+    log(f"case c4 full size: sum n = {sum(i.n for i in insts)}")
+    probs = [pcls.Problem.from_instance(i) for i in insts]
+    R, lr = 64, 0.1
+    states = []
+    for k, p in enumerate(probs):
+        X = p.new_state(R)
+        p.init_restarts(X, R, 4000 + k)
+        states.append(X)
+    x0 = {k: rows_of(states[k], R) for k in (0, 77, 255)}
+    traces = [torch.zeros((1, R), device=X.device) for X in states]
+    b = Batch(probs, [R] * len(probs), states, traces)
+    b.autotune(lr, probe_steps=2)
+    b.capture(lr, 1)
+    b.replay()
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(0)
+    for k, x in x0.items():
+        rs = np.sort(rng.choice(R, 6, replace=False))
+        ref = oracle_for(insts[k]).evaluate(x[rs], method=N.PMF)
+        assert_obj_grad(traces[k][0].cpu().numpy()[rs], None, ref, what=f"c4 instance {k}", inst=insts[k])
+        expect = np.clip(x[rs] - lr * ref["grad"], -1, 1)
+        got = rows_of(states[k], R)[rs]
+        slack = lr * TOL * np.maximum(np.abs(ref["grad"]), range_scales(insts[k])[1]) + 2.0 ** -22
+        assert np.all(np.abs(got - expect) <= slack), k
