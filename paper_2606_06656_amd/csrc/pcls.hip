@@ -460,17 +460,20 @@ __device__ __forceinline__ void prod_pair_r2(const Fetched<KMAX>& fp, int t2, in
   const float a1 = pp.a, b1 = pp.b, c1 = pp.c1, c2 = pp.c2;
   unsigned el[J];
   float fa1[J], fb1[J], fa2[J], fb2[J];
+  // the literal's sign goes onto the node coefficient (and below onto the
+  // gradient scale) once for both restarts: b (s x) = (s b) x exactly
 #pragma unroll
   for (int j = 0; j < J; ++j) {
     el[j] = lit_off(fp.code[j], logT, 2 * t2);
     const float2 xv = *reinterpret_cast<const float2*>(reinterpret_cast<const char*>(xs) + el[j]);
     const unsigned sb = lit_sign(fp.code[j]);
-    const float ya = flip(xv.x, sb), yb = flip(xv.y, sb);
-    fa1[j] = fmaf(b1, ya, a1);
-    fb1[j] = fmaf(b1, yb, a1);
+    const float bj = flip(b1, sb);
+    fa1[j] = fmaf(bj, xv.x, a1);
+    fb1[j] = fmaf(bj, xv.y, a1);
     if constexpr (NN == 2) {
-      fa2[j] = fmaf(-0.5f, ya, 0.5f);
-      fb2[j] = fmaf(-0.5f, yb, 0.5f);
+      const float hj = flip(-0.5f, sb);
+      fa2[j] = fmaf(hj, xv.x, 0.5f);
+      fb2[j] = fmaf(hj, xv.y, 0.5f);
     }
   }
   float pa1[J], pb1[J], pa2[J], pb2[J];
@@ -501,19 +504,21 @@ __device__ __forceinline__ void prod_pair_r2(const Fetched<KMAX>& fp, int t2, in
   float sa1 = 1.f, sb1 = 1.f, sa2 = 1.f, sb2 = 1.f;
 #pragma unroll
   for (int j = J - 1; j >= 0; --j) {
-    float ga = s1 * pa1[j] * sa1, gb = s1 * pb1[j] * sb1;
+    const unsigned sg = lit_sign(fp.code[j]);
+    const float s1j = flip(s1, sg);  // dF/dx = s dF/dy
+    float ga = s1j * pa1[j] * sa1, gb = s1j * pb1[j] * sb1;
     sa1 *= fa1[j];
     sb1 *= fb1[j];
     if constexpr (NN == 2) {
-      ga = fmaf(s2 * pa2[j], sa2, ga);
-      gb = fmaf(s2 * pb2[j], sb2, gb);
+      const float s2j = flip(s2, sg);
+      ga = fmaf(s2j * pa2[j], sa2, ga);
+      gb = fmaf(s2j * pb2[j], sb2, gb);
       sa2 *= fa2[j];
       sb2 *= fb2[j];
     }
-    const unsigned sg = lit_sign(fp.code[j]);
     AT* gp = g_at(gs, el[j]);
-    FixedAcc<AT>::add(gp, flip(ga, sg));
-    FixedAcc<AT>::add(gp + 1, flip(gb, sg));
+    FixedAcc<AT>::add(gp, ga);
+    FixedAcc<AT>::add(gp + 1, gb);
   }
 }
 
