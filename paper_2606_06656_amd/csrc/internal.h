@@ -66,7 +66,7 @@ struct Segment {
   int32_t lit_base;   // offset of the segment's transposed literal block
   int32_t k_fixed;    // > 0 when every constraint has this length
   int32_t cls_fixed;  // >= 0 when every constraint has this class
-  int32_t m_max;      // DFT: largest number of complex nodes over the segment
+  int32_t m_max;      // DFT: largest number of complex nodes; PMF: widest window over the segment
 };
 
 // Per constraint class (type, k, param).
@@ -75,7 +75,7 @@ struct ClassRec {
   int32_t k;
   int32_t n_nodes;   // DFT: complex nodes m = 1..n_nodes
   int32_t node_off;  // DFT: offset into the node table (entries)
-  int32_t nyquist;   // DFT: 1 when K = k + 1 is even (real node at omega = -1)
+  int32_t nyquist;   // DFT: 1 when K = k + 1 is even (real node at omega = -1); PMF: window w
   int32_t sp_off;    // offset of sp[0..k] (int8) in the spectrum table
   float a, b;        // PROD1 node factor a + b y
   float c1, c2;      // PROD1 / PROD2 product weights; DFT: c1 = chat_{K/2} (Nyquist weight)

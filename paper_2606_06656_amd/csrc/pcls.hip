@@ -397,19 +397,27 @@ __device__ __forceinline__ void dft_pair(const ProblemDev& P, int m_max, int cls
 // dFE/dpi_i = sum_c pre_i[c] (lambda_{c+1} - lambda_c) (lambda_4 = 0) where pre_i
 // is q before literal i, then lambda_c <- lambda_c + pi_i (lambda_{c+1} - lambda_c).
 // Every update is a convex combination, so no cancellation arises.
-template <int KMAX, class SK>
+// W: counts kept, the widest window of the segment (coefficients past a class's
+// own window are zero, so a wider W changes no value).
+template <int KMAX, int W, class SK>
 __device__ __forceinline__ void pmf_pair(const ProblemDev& P, int cls, const Fetched<KMAX>& fp, int t, int logT,
                                          const float* xs, SK& sink, float& fchunk, float gsc, float fsc) {
   constexpr int J = KMAX;  // buckets up to 8 hold a single length
-  constexpr int W = kPmfWindow;
+  static_assert(W >= 1 && W <= kPmfWindow, "window");
   kptr<ClassRec> classes = kconst(P.classes);
   kptr<NodeRec> nd = kconst(P.nodes) + classes[cls].node_off;
-  float d[W] = {nd[0].ar, nd[0].ai, nd[0].br, nd[0].bi};
+  const float dall[kPmfWindow] = {nd[0].ar, nd[0].ai, nd[0].br, nd[0].bi};
+  float d[W];
+#pragma unroll
+  for (int c = 0; c < W; ++c) d[c] = dall[c];
   const float h = nd[0].wr;
 
   unsigned el[J];
   float pi[J], pre[J][W];
-  float q[W] = {1.f, 0.f, 0.f, 0.f};
+  float q[W];
+  q[0] = 1.f;
+#pragma unroll
+  for (int c = 1; c < W; ++c) q[c] = 0.f;
 #pragma unroll
   for (int j = 0; j < J; ++j) {
     el[j] = lit_off(fp.code[j], logT, t);
@@ -666,7 +674,15 @@ __device__ __forceinline__ void run_segment(const ProblemDev& P, const Segment& 
             dft_pair<KMAX, G>(P, S.m_max, f.cls, f, lig, t, logT, xs, sink, fchunk, gsc, fsc);
           }
         } else if constexpr (KIND == KIND_PMF) {
-          pmf_pair<KMAX>(P, chunk_uni ? c0 : f.cls, f, t, logT, xs, sink, fchunk, gsc, fsc);
+          // window width of the segment (uniform): 2, 3 or 4 counts
+          const int cls = chunk_uni ? c0 : f.cls;
+          if (S.m_max <= 2) {
+            pmf_pair<KMAX, 2>(P, cls, f, t, logT, xs, sink, fchunk, gsc, fsc);
+          } else if (S.m_max == 3) {
+            pmf_pair<KMAX, 3>(P, cls, f, t, logT, xs, sink, fchunk, gsc, fsc);
+          } else {
+            pmf_pair<KMAX, 4>(P, cls, f, t, logT, xs, sink, fchunk, gsc, fsc);
+          }
         } else {
           const ProdParams pp = uni ? pp_uni : prod_params(classes, chunk_uni ? c0 : f.cls);
           prod_pair<KIND == KIND_PROD2 ? 2 : 1, KMAX, G>(f, lig, t, logT, xs, sink, fchunk, gsc, fsc, pp);

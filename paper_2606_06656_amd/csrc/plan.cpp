@@ -328,7 +328,7 @@ int32_t build_plan(int32_t n, int32_t m, const int32_t* row_ptr, const int32_t* 
       if (C.kind == KIND_PMF) {
         NodeRec N{};
         float d[kPmfWindow], h;
-        pmf_window(sp, d, &h);
+        C.nyquist = pmf_window(sp, d, &h);  // PMF: the window w (counts kept)
         N.ar = d[0];
         N.ai = d[1];
         N.br = d[2];
@@ -460,6 +460,7 @@ int32_t build_plan(int32_t n, int32_t m, const int32_t* row_ptr, const int32_t* 
       if (C.k != S.k_fixed) S.k_fixed = 0;
       if (P->c_cls[e] != S.cls_fixed) S.cls_fixed = -1;
       if (C.kind == KIND_DFT) S.m_max = std::max(S.m_max, C.n_nodes);
+      if (C.kind == KIND_PMF) S.m_max = std::max(S.m_max, C.nyquist);
       ++e;
     }
     S.c_count = e - j;
