@@ -101,12 +101,66 @@ __device__ __forceinline__ long long fixed_term(float v) {
 // The G lanes of one (constraint, restart) pair sit at stride T in the wave:
 // lane = base + lig * T.  Exclusive prefix / suffix products of one value per
 // lane (Hillis-Steele over log2 G shuffle steps).
+// Group scans.  A pair's G lanes sit at stride T inside the wave (lane =
+// t + T * (lig + G * sub)).  With T = 1 and G <= 16 a group lies inside one
+// 16-lane row, and each scan step is a DPP row shift (one VALU move, no LDS);
+// otherwise the steps are wave shuffles.  Both paths multiply in the same order,
+// so the results are identical bit for bit.
+template <int D>
+__device__ __forceinline__ float row_shr(float v) {  // lane l reads lane l - D of its row
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x110 + D, 0xf, 0xf, true));
+}
+template <int D>
+__device__ __forceinline__ float row_shl(float v) {  // lane l reads lane l + D of its row
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x100 + D, 0xf, 0xf, true));
+}
+
+template <int G, int D = 1>
+__device__ __forceinline__ void prefix_steps_dpp(float& inc, int lig) {
+  if constexpr (D < G) {
+    const float o = row_shr<D>(inc);
+    if (lig >= D) inc *= o;
+    prefix_steps_dpp<G, 2 * D>(inc, lig);
+  }
+}
+template <int G, int D = 1>
+__device__ __forceinline__ void suffix_steps_dpp(float& inc, int lig) {
+  if constexpr (D < G) {
+    const float o = row_shl<D>(inc);
+    if (lig + D < G) inc *= o;
+    suffix_steps_dpp<G, 2 * D>(inc, lig);
+  }
+}
+template <int G, int D = 1>
+__device__ __forceinline__ void prefix_steps_dpp_c(cf& inc, int lig) {
+  if constexpr (D < G) {
+    const cf o{row_shr<D>(inc.r), row_shr<D>(inc.i)};
+    if (lig >= D) inc = cmul(o, inc);
+    prefix_steps_dpp_c<G, 2 * D>(inc, lig);
+  }
+}
+template <int G, int D = 1>
+__device__ __forceinline__ void suffix_steps_dpp_c(cf& inc, int lig) {
+  if constexpr (D < G) {
+    const cf o{row_shl<D>(inc.r), row_shl<D>(inc.i)};
+    if (lig + D < G) inc = cmul(inc, o);
+    suffix_steps_dpp_c<G, 2 * D>(inc, lig);
+  }
+}
+
 template <int G>
 __device__ __forceinline__ float grp_prefix(float v, int lig, int T) {
   if constexpr (G == 1) {
     return 1.f;
   } else {
     float inc = v;
+    if constexpr (G <= 16) {
+      if (T == 1) {
+        prefix_steps_dpp<G>(inc, lig);
+        const float ex = row_shr<1>(inc);
+        return lig == 0 ? 1.f : ex;
+      }
+    }
 #pragma unroll
     for (int d = 1; d < G; d <<= 1) {
       float o = __shfl_up(inc, d * T);
@@ -123,6 +177,13 @@ __device__ __forceinline__ float grp_suffix(float v, int lig, int T) {
     return 1.f;
   } else {
     float inc = v;
+    if constexpr (G <= 16) {
+      if (T == 1) {
+        suffix_steps_dpp<G>(inc, lig);
+        const float ex = row_shl<1>(inc);
+        return lig == G - 1 ? 1.f : ex;
+      }
+    }
 #pragma unroll
     for (int d = 1; d < G; d <<= 1) {
       float o = __shfl_down(inc, d * T);
@@ -139,6 +200,13 @@ __device__ __forceinline__ cf grp_prefix_c(cf v, int lig, int T) {
     return {1.f, 0.f};
   } else {
     cf inc = v;
+    if constexpr (G <= 16) {
+      if (T == 1) {
+        prefix_steps_dpp_c<G>(inc, lig);
+        const cf ex{row_shr<1>(inc.r), row_shr<1>(inc.i)};
+        return lig == 0 ? cf{1.f, 0.f} : ex;
+      }
+    }
 #pragma unroll
     for (int d = 1; d < G; d <<= 1) {
       cf o{__shfl_up(inc.r, d * T), __shfl_up(inc.i, d * T)};
@@ -155,6 +223,13 @@ __device__ __forceinline__ cf grp_suffix_c(cf v, int lig, int T) {
     return {1.f, 0.f};
   } else {
     cf inc = v;
+    if constexpr (G <= 16) {
+      if (T == 1) {
+        suffix_steps_dpp_c<G>(inc, lig);
+        const cf ex{row_shl<1>(inc.r), row_shl<1>(inc.i)};
+        return lig == G - 1 ? cf{1.f, 0.f} : ex;
+      }
+    }
 #pragma unroll
     for (int d = 1; d < G; d <<= 1) {
       cf o{__shfl_down(inc.r, d * T), __shfl_down(inc.i, d * T)};

@@ -373,3 +373,32 @@ def test_short_types_two_restart_lanes(T):
     prob.set_launch(1, 512)
     prob.step(X2, R, 0.1, 5)
     assert torch.equal(X1[:, :R], X2[:, :R])
+
+
+@pytest.mark.parametrize("T,kmax", [(2, 256), (4, 128), (8, 64)])
+def test_long_types_lane_groups_across_tile_widths(T, kmax):
+    """Constraints spread over groups of up to 32 lanes (DFT and long products):
+    at tile widths T >= 2 the group scans run as wave shuffles, at T = 1 as row
+    shifts inside 16-lane rows.  Both agree with the oracle and give bitwise
+    equal gradients and iterates.  (T times the group width must fit one wave.)"""
+    inst = synth.mixed_small(n=300, seed=41, kmax=kmax, count=120)
+    log(f"case long types T={T} m={inst.m} L={inst.L}")
+    prob = pcls.Problem.from_instance(inst)
+    kinds = dict(zip(pcls.KIND_NAMES, prob.info().cons_by_kind))
+    assert kinds["dft"] > 0 and kinds["prod1"] > 0
+    R = 64
+    x = corner_mix(np.random.default_rng(41), R, inst.n)
+    X = prob.state_from_rows(x)
+    prob.set_launch(T, 512)
+    obj, grad = prob.evaluate(X, R)
+    ref = oracle_for(inst).evaluate(rows_of(X, R), method=N.PMF)
+    assert_obj_grad(obj.cpu().numpy(), grad[:, :R].T.cpu().numpy(), ref, what=f"long T={T}", inst=inst)
+    prob.set_launch(1, 512)
+    _, g1 = prob.evaluate(X, R)
+    assert torch.equal(grad[:, :R], g1[:, :R])
+    X1, X2 = X.clone(), X.clone()
+    prob.set_launch(T, 512)
+    prob.step(X1, R, 0.1, 4)
+    prob.set_launch(1, 512)
+    prob.step(X2, R, 0.1, 4)
+    assert torch.equal(X1[:, :R], X2[:, :R])
