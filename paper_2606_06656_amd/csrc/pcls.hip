@@ -98,11 +98,9 @@ __device__ __forceinline__ long long fixed_term(float v) {
 }
 
 // ---------------------------------------------------------------- group scans
-// The G lanes of one (constraint, restart) pair sit at stride T in the wave:
-// lane = base + lig * T.  Exclusive prefix / suffix products of one value per
-// lane (Hillis-Steele over log2 G shuffle steps).
-// Group scans.  A pair's G lanes sit at stride T inside the wave (lane =
-// t + T * (lig + G * sub)).  With T = 1 and G <= 16 a group lies inside one
+// Exclusive prefix / suffix products of one value per lane over the G lanes of
+// one (constraint, restart) pair (Hillis-Steele, log2 G steps).  A pair's G
+// lanes sit at stride T inside the wave (lane = t + T * (lig + G * sub)).  With T = 1 and G <= 16 a group lies inside one
 // 16-lane row, and each scan step is a DPP row shift (one VALU move, no LDS);
 // otherwise the steps are wave shuffles.  Both paths multiply in the same order,
 // so the results are identical bit for bit.
@@ -853,8 +851,52 @@ struct TileArgs {
   int* iters;           // [R] or NULL: steps until convergence (n_steps if never)
 };
 
+// In the variants for short constraints, whose steps are short enough for the
+// end-of-step reduction to matter, objective partial sums leave the lanes in
+// two stages without wave shuffles (those go through the LDS crossbar, which
+// all waves of the tile would contend for at once).  Within each 16-lane
+// row, DPP row shifts (VALU only, no LDS traffic) add up the lanes of equal
+// index mod P, so the top P lanes of the row hold the row's sums (P >= 16:
+// nothing to fold).  Those lanes then add into 64-bit LDS slots, slot
+// r * P + (lane mod P) for row r (P >= 16: slot = lane): at most 4 slots per
+// residue, all distinct within a wave.  Integer sums are exact in any order.
+template <int D>
+__device__ __forceinline__ unsigned long long add_row_shr(unsigned long long v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)v, 0x110 + D, 0xf, 0xf, true);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(v >> 32), 0x110 + D, 0xf, 0xf, true);
+  return v + (((unsigned long long)(unsigned)hi << 32) | (unsigned)lo);
+}
+__device__ __forceinline__ unsigned long long row_fold(unsigned long long v, int P) {
+  if (P <= 1) v = add_row_shr<1>(v);
+  if (P <= 2) v = add_row_shr<2>(v);
+  if (P <= 4) v = add_row_shr<4>(v);
+  if (P <= 8) v = add_row_shr<8>(v);
+  return v;
+}
+// slot of this lane's folded sum, or -1 (lanes whose row sum sits elsewhere)
+__device__ __forceinline__ int fold_slot(int lane, int P) {
+  if (P >= 16) return lane;
+  const int c = lane & 15;
+  return c >= 16 - P ? (lane >> 4) * P + (c - (16 - P)) : -1;
+}
+// sum and clear the slots of residue q (slots q + r P, r < min(4, 64 / P))
+__device__ __forceinline__ unsigned long long take_slots(unsigned long long* sl, int q, int P) {
+  const int nper = P >= 16 ? kWave / P : 4;
+  unsigned long long a[4] = {0ull, 0ull, 0ull, 0ull};
+#pragma unroll
+  for (int r = 0; r < 4; ++r)
+    if (r < nper) a[r] = sl[q + r * P];
+#pragma unroll
+  for (int r = 0; r < 4; ++r)
+    if (r < nper) sl[q + r * P] = 0ull;
+  return (a[0] + a[1]) + (a[2] + a[3]);
+}
+
 // All n_steps steps of one tile with its state in LDS.
-// LDS: x[n][T] float | g[n][T] fixed point | F[T] 64-bit fixed point |
+// LDS: x[n][T] float | g[n][T] fixed point | objective slots (64-bit fixed
+//      point, 64 per set; a second and third set, for the even and odd
+//      restarts of two-restart lanes, when T >= 2; the long-constraint
+//      variants use slot t for restart t) |
 //      one work counter per segment | per restart: converged flag, max |dx|.
 template <int MAXB, class AT>
 __device__ __forceinline__ void resident_tile(const ProblemDev& P, const TileArgs& A, unsigned long long* lds_raw) {
@@ -863,9 +905,10 @@ __device__ __forceinline__ void resident_tile(const ProblemDev& P, const TileArg
   const int NT = P.n << logT;
   float* xs = reinterpret_cast<float*>(lds_raw);
   AT* gs = reinterpret_cast<AT*>(reinterpret_cast<char*>(lds_raw) + ((size_t)NT * 4 + 7) / 8 * 8);
-  unsigned long long* Fs =
+  unsigned long long* Fl =
       reinterpret_cast<unsigned long long*>(reinterpret_cast<char*>(gs) + ((size_t)NT * sizeof(AT) + 7) / 8 * 8);
-  int* ctr = reinterpret_cast<int*>(Fs + T);
+  const int n_fl = logT >= 1 ? 3 * kWave : kWave;
+  int* ctr = reinterpret_cast<int*>(Fl + n_fl);
   int* conv = ctr + kMaxSegments;
   unsigned int* dxmax = reinterpret_cast<unsigned int*>(conv + T);
   const int tid = threadIdx.x, nth = blockDim.x;
@@ -881,8 +924,8 @@ __device__ __forceinline__ void resident_tile(const ProblemDev& P, const TileArg
     xs[i] = x;
     gs[i] = 0;
   }
+  for (int i = tid; i < n_fl; i += nth) Fl[i] = 0ull;
   if (tid < T) {
-    Fs[tid] = 0ull;
     conv[tid] = 0;
     dxmax[tid] = 0u;
   }
@@ -898,27 +941,47 @@ __device__ __forceinline__ void resident_tile(const ProblemDev& P, const TileArg
                       segs[sg].lit_base, segs[sg].k_fixed, segs[sg].cls_fixed, segs[sg].m_max};
       run_any_segment<MAXB>(P, S, xs, gs, facc, A.gsc, A.fsc, tid, logT, ctr + sg);
     }
-    // lanes with equal (lane mod T) hold the same restart; integer sums are exact
-    for (int o = T; o < kWave; o <<= 1) facc.own += __shfl_xor(facc.own, o);
-    if ((tid & (kWave - 1)) < T) atomicAdd(&Fs[t], (unsigned long long)facc.own);
     if constexpr (MAXB <= kMaxbShort) {
-      if (logT >= 1) {  // two-restart lanes: restarts 2 t2 and 2 t2 + 1, t2 = lane mod T/2
-        for (int o = T >> 1; o < kWave; o <<= 1) {
-          facc.even += __shfl_xor(facc.even, o);
-          facc.odd += __shfl_xor(facc.odd, o);
-        }
-        const int l = tid & (kWave - 1);
-        if (l < (T >> 1)) {
-          atomicAdd(&Fs[2 * l], (unsigned long long)facc.even);
-          atomicAdd(&Fs[2 * l + 1], (unsigned long long)facc.odd);
+      // restart of a lane's own terms: lane mod T; of its two-restart terms:
+      // 2 (lane mod T/2) (even) and 2 (lane mod T/2) + 1 (odd).
+      // (opaque lane index: slot addresses are recomputed here each step instead
+      // of being kept live through the segment loops)
+      int l = tid & (kWave - 1);
+      asm volatile("" : "+v"(l));
+      const unsigned long long vo = row_fold((unsigned long long)facc.own, T);
+      const int so = fold_slot(l, T);
+      if (so >= 0) atomicAdd(&Fl[so], vo);
+      if (logT >= 1) {
+        const unsigned long long ve = row_fold((unsigned long long)facc.even, T >> 1);
+        const unsigned long long vd = row_fold((unsigned long long)facc.odd, T >> 1);
+        const int s2 = fold_slot(l, T >> 1);
+        if (s2 >= 0) {
+          atomicAdd(&Fl[kWave + s2], ve);
+          atomicAdd(&Fl[2 * kWave + s2], vd);
         }
       }
+    } else {
+      // variants for long constraints: a step's work dwarfs this reduction, and
+      // the shuffle form leaves the register allocation of their long loops
+      // unchanged (the row fold above made them spill more)
+      for (int o = T; o < kWave; o <<= 1) facc.own += __shfl_xor(facc.own, o);
+      if ((tid & (kWave - 1)) < T) atomicAdd(&Fl[t], (unsigned long long)facc.own);
     }
     __syncthreads();
     if (tid < n_seg) ctr[tid] = 0;  // every wave has left the segment loops
     if (tid < T) {
-      const float F = FixedAcc<unsigned long long>::value_exact(Fs[tid], A.finv) + P.f_const;
-      Fs[tid] = 0ull;
+      // each slot has one reader, which clears it for the next step
+      unsigned long long acc;
+      if constexpr (MAXB <= kMaxbShort) {
+        int q = t;
+        asm volatile("" : "+v"(q));
+        acc = take_slots(Fl, q, T);
+        if (logT >= 1) acc += take_slots(Fl + ((q & 1) ? 2 * kWave : kWave), q >> 1, T >> 1);
+      } else {
+        acc = Fl[t];
+        Fl[t] = 0ull;
+      }
+      const float F = FixedAcc<unsigned long long>::value_exact(acc, A.finv) + P.f_const;
       const int r = r0 + tid;
       F_last = F;
       if (r < A.R) {
@@ -1299,7 +1362,8 @@ int32_t device_limits(DeviceLimits& out) {
 // F[T] 64-bit, each region 8-byte aligned.
 size_t tile_lds_bytes(int n, int T, int acc_bytes) {
   const size_t nt = (size_t)n * T;
-  return (nt * 4 + 7) / 8 * 8 + (nt * acc_bytes + 7) / 8 * 8 + (size_t)T * 8 + 4 * kMaxSegments + (size_t)T * 8;
+  const size_t slots = (T >= 2 ? 3 : 1) * (size_t)kWave * 8;  // objective slots
+  return (nt * 4 + 7) / 8 * 8 + (nt * acc_bytes + 7) / 8 * 8 + slots + 4 * kMaxSegments + (size_t)T * 8;
 }
 
 struct Launch {
