@@ -311,6 +311,18 @@ __device__ __forceinline__ ProdParams prod_params(kptr<ClassRec> classes, int cl
   return {classes[cls].a, classes[cls].b, classes[cls].c1, classes[cls].c2};
 }
 
+// The same with the fixed-point scales folded in once per class: f = c fsc for
+// the objective, s1 = c1 b gsc and s2 = -c2/2 gsc for the gradient.  The scales
+// are powers of two, so every product equals the one formed by scaling last.
+struct ProdConsts {
+  float a, b, f1, f2, s1, s2;
+};
+
+__device__ __forceinline__ ProdConsts prod_consts(kptr<ClassRec> classes, int cls, float gsc, float fsc) {
+  const float a = classes[cls].a, b = classes[cls].b, c1 = classes[cls].c1, c2 = classes[cls].c2;
+  return {a, b, c1 * fsc, c2 * fsc, c1 * b * gsc, -0.5f * c2 * gsc};
+}
+
 template <int NN, int KMAX, int G, class SK>
 __device__ __forceinline__ void prod_pair(const Fetched<KMAX / G>& fp, int lig, int t, int logT, const float* xs, SK& sink,
                                           float& fchunk, float gsc, float fsc, const ProdParams& pp) {
@@ -534,11 +546,11 @@ struct ObjAcc {
 // codes, the address decode, the claim and the loop control are shared by two
 // literal-evaluations; x of both restarts arrives in one 8-byte LDS read and the
 // second gradient term goes to the next LDS word.
-template <int NN, int KMAX, class AT>
+template <int NN, int KMAX, bool UW, class AT>
 __device__ __forceinline__ void prod_pair_r2(const Fetched<KMAX>& fp, int t2, int logT, const float* xs, AT* gs,
-                                             float& fca, float& fcb, float gsc, float fsc, const ProdParams& pp) {
+                                             float& fca, float& fcb, const ProdConsts& pc) {
   constexpr int J = KMAX;  // one lane per pair, every slot filled (buckets up to 8 hold one length)
-  const float a1 = pp.a, b1 = pp.b, c1 = pp.c1, c2 = pp.c2;
+  const float a1 = pc.a, b1 = pc.b;
   unsigned el[J];
   float fa1[J], fb1[J], fa2[J], fb2[J];
   // the literal's sign goes onto the node coefficient (and below onto the
@@ -572,16 +584,26 @@ __device__ __forceinline__ void prod_pair_r2(const Fetched<KMAX>& fp, int t2, in
       rb2 *= fb2[j];
     }
   }
-  float fea = c1 * ra1, feb = c1 * rb1;
-  if constexpr (NN == 2) {
-    fea = fmaf(c2, ra2, fea);
-    feb = fmaf(c2, rb2, feb);
+  // objective w (c1 P1 [+ c2 P2]) fsc; unit weights: one FMA per restart and node
+  float s1 = pc.s1, s2 = pc.s2;
+  if constexpr (UW) {
+    if constexpr (NN == 2) {
+      fca = fmaf(pc.f2, ra2, fca);
+      fcb = fmaf(pc.f2, rb2, fcb);
+    }
+    fca = fmaf(pc.f1, ra1, fca);
+    fcb = fmaf(pc.f1, rb1, fcb);
+  } else {
+    float fea = pc.f1 * ra1, feb = pc.f1 * rb1;
+    if constexpr (NN == 2) {
+      fea = fmaf(pc.f2, ra2, fea);
+      feb = fmaf(pc.f2, rb2, feb);
+    }
+    fca = fmaf(fp.w, fea, fca);
+    fcb = fmaf(fp.w, feb, fcb);
+    s1 *= fp.w;
+    s2 *= fp.w;
   }
-  const float wf = fp.w * fsc;
-  fca = fmaf(wf, fea, fca);
-  fcb = fmaf(wf, feb, fcb);
-  const float s1 = c1 * b1 * (fp.w * gsc);
-  const float s2 = -0.5f * c2 * (fp.w * gsc);
   float sa1 = 1.f, sb1 = 1.f, sa2 = 1.f, sb2 = 1.f;
 #pragma unroll
   for (int j = J - 1; j >= 0; --j) {
@@ -619,7 +641,7 @@ struct FetchedU {
 };
 
 // The two-restarts-per-lane variant of run_segment for short product kinds.
-template <int KIND, int KMAX, class AT>
+template <int KIND, int KMAX, bool UW, class AT>
 __device__ __forceinline__ void run_segment_r2(const ProblemDev& P, const Segment& S, const float* xs, AT* gs,
                                                ObjAcc& facc, float gsc, float fsc, int tid, int logT, int* ctr) {
   constexpr int J = KMAX;
@@ -631,8 +653,8 @@ __device__ __forceinline__ void run_segment_r2(const ProblemDev& P, const Segmen
   const int per_wave = kWave >> (logT - 1);
   kptr<ClassRec> classes = kconst(P.classes);
   const bool uni = S.cls_fixed >= 0;
-  ProdParams pp_uni{};
-  if (uni) pp_uni = prod_params(classes, S.cls_fixed);
+  ProdConsts pc_uni{};
+  if (uni) pc_uni = prod_consts(classes, S.cls_fixed, gsc, fsc);
   auto claim = [&]() {
     int b = 0;
     if (lane == 0) b = atomicAdd(ctr, U * per_wave);
@@ -659,8 +681,8 @@ __device__ __forceinline__ void run_segment_r2(const ProblemDev& P, const Segmen
       const int c0 = __builtin_amdgcn_readfirstlane(fp.cls);
       const bool chunk_uni = uni || !__any(valid && fp.cls != c0);
       if (valid) {
-        const ProdParams pp = uni ? pp_uni : prod_params(classes, chunk_uni ? c0 : fp.cls);
-        prod_pair_r2<KIND == KIND_PROD2 ? 2 : 1, KMAX>(fp, t2, logT, xs, gs, fca, fcb, gsc, fsc, pp);
+        const ProdConsts pc = uni ? pc_uni : prod_consts(classes, chunk_uni ? c0 : fp.cls, gsc, fsc);
+        prod_pair_r2<KIND == KIND_PROD2 ? 2 : 1, KMAX, UW>(fp, t2, logT, xs, gs, fca, fcb, pc);
       }
     }
     facc.even += fixed_term(fca);
@@ -683,7 +705,11 @@ __device__ __forceinline__ void run_segment(const ProblemDev& P, const Segment& 
                                             StatsOut so = {}) {
   if constexpr (!ST && (KIND == KIND_PROD1 || KIND == KIND_PROD2) && MAXB <= kMaxbShort && KMAX <= 8) {
     if (logT >= 1) {
-      run_segment_r2<KIND, KMAX>(P, S, xs, gs, facc, gsc, fsc, tid, logT, ctr);
+      // unit weights (a problem-wide flag): no weight fetch or multiply
+      if (P.unit_weights)
+        run_segment_r2<KIND, KMAX, true>(P, S, xs, gs, facc, gsc, fsc, tid, logT, ctr);
+      else
+        run_segment_r2<KIND, KMAX, false>(P, S, xs, gs, facc, gsc, fsc, tid, logT, ctr);
       return;
     }
   }
