@@ -919,10 +919,10 @@ __device__ __forceinline__ unsigned long long take_slots(unsigned long long* sl,
 }
 
 // All n_steps steps of one tile with its state in LDS.
-// LDS: x[n][T] float | g[n][T] fixed point | objective slots (64-bit fixed
-//      point, 64 per set; a second and third set, for the even and odd
-//      restarts of two-restart lanes, when T >= 2; the long-constraint
-//      variants use slot t for restart t) |
+// LDS: x[n][T] float | g[n][T] fixed point | two slot sets for the objective
+//      (64-bit fixed point; per set 64 slots, and 2 x 64 more for the even and
+//      odd restarts of two-restart lanes when T >= 2; the long-constraint
+//      variants use slot t of set 0 for restart t) |
 //      one work counter per segment | per restart: converged flag, max |dx|.
 template <int MAXB, class AT>
 __device__ __forceinline__ void resident_tile(const ProblemDev& P, const TileArgs& A, unsigned long long* lds_raw) {
@@ -933,8 +933,8 @@ __device__ __forceinline__ void resident_tile(const ProblemDev& P, const TileArg
   AT* gs = reinterpret_cast<AT*>(reinterpret_cast<char*>(lds_raw) + ((size_t)NT * 4 + 7) / 8 * 8);
   unsigned long long* Fl =
       reinterpret_cast<unsigned long long*>(reinterpret_cast<char*>(gs) + ((size_t)NT * sizeof(AT) + 7) / 8 * 8);
-  const int n_fl = logT >= 1 ? 3 * kWave : kWave;
-  int* ctr = reinterpret_cast<int*>(Fl + n_fl);
+  const int n_fl = logT >= 1 ? 3 * kWave : kWave;  // slots per set; two sets
+  int* ctr = reinterpret_cast<int*>(Fl + 2 * n_fl);
   int* conv = ctr + kMaxSegments;
   unsigned int* dxmax = reinterpret_cast<unsigned int*>(conv + T);
   const int tid = threadIdx.x, nth = blockDim.x;
@@ -950,7 +950,7 @@ __device__ __forceinline__ void resident_tile(const ProblemDev& P, const TileArg
     xs[i] = x;
     gs[i] = 0;
   }
-  for (int i = tid; i < n_fl; i += nth) Fl[i] = 0ull;
+  for (int i = tid; i < 2 * n_fl; i += nth) Fl[i] = 0ull;
   if (tid < T) {
     conv[tid] = 0;
     dxmax[tid] = 0u;
@@ -959,14 +959,11 @@ __device__ __forceinline__ void resident_tile(const ProblemDev& P, const TileArg
   __syncthreads();
   float F_last = 0.f;  // threads tid < T: last evaluated objective of restart r0 + tid
 
-  for (int s = 0; s < A.n_steps; ++s) {
-    ObjAcc facc{0, 0, 0};
-    kptr<Segment> segs = kconst(P.segments);
-    for (int sg = 0; sg < n_seg; ++sg) {
-      const Segment S{segs[sg].kind,    segs[sg].bucket, segs[sg].c_begin,   segs[sg].c_count,
-                      segs[sg].lit_base, segs[sg].k_fixed, segs[sg].cls_fixed, segs[sg].m_max};
-      run_any_segment<MAXB>(P, S, xs, gs, facc, A.gsc, A.fsc, tid, logT, ctr + sg);
-    }
+  // The objective of step s goes through slot set s mod 2.  deposit: every wave
+  // adds its lanes' partial sums; finalize: thread t < T, once every deposit of
+  // that step has landed, sums and clears restart t's slots and writes F.
+  auto set_of = [&](int step) { return Fl + (step & 1) * n_fl; };
+  auto deposit = [&](const ObjAcc& fa, unsigned long long* sl) {
     if constexpr (MAXB <= kMaxbShort) {
       // restart of a lane's own terms: lane mod T; of its two-restart terms:
       // 2 (lane mod T/2) (even) and 2 (lane mod T/2) + 1 (odd).
@@ -974,46 +971,76 @@ __device__ __forceinline__ void resident_tile(const ProblemDev& P, const TileArg
       // of being kept live through the segment loops)
       int l = tid & (kWave - 1);
       asm volatile("" : "+v"(l));
-      const unsigned long long vo = row_fold((unsigned long long)facc.own, T);
+      const unsigned long long vo = row_fold((unsigned long long)fa.own, T);
       const int so = fold_slot(l, T);
-      if (so >= 0) atomicAdd(&Fl[so], vo);
+      if (so >= 0) atomicAdd(&sl[so], vo);
       if (logT >= 1) {
-        const unsigned long long ve = row_fold((unsigned long long)facc.even, T >> 1);
-        const unsigned long long vd = row_fold((unsigned long long)facc.odd, T >> 1);
+        const unsigned long long ve = row_fold((unsigned long long)fa.even, T >> 1);
+        const unsigned long long vd = row_fold((unsigned long long)fa.odd, T >> 1);
         const int s2 = fold_slot(l, T >> 1);
         if (s2 >= 0) {
-          atomicAdd(&Fl[kWave + s2], ve);
-          atomicAdd(&Fl[2 * kWave + s2], vd);
+          atomicAdd(&sl[kWave + s2], ve);
+          atomicAdd(&sl[2 * kWave + s2], vd);
         }
       }
     } else {
       // variants for long constraints: a step's work dwarfs this reduction, and
       // the shuffle form leaves the register allocation of their long loops
       // unchanged (the row fold above made them spill more)
-      for (int o = T; o < kWave; o <<= 1) facc.own += __shfl_xor(facc.own, o);
-      if ((tid & (kWave - 1)) < T) atomicAdd(&Fl[t], (unsigned long long)facc.own);
+      unsigned long long v = (unsigned long long)fa.own;
+      for (int o = T; o < kWave; o <<= 1) v += __shfl_xor(v, o);
+      if ((tid & (kWave - 1)) < T) atomicAdd(&sl[t], v);
     }
+  };
+  auto finalize = [&](int step, unsigned long long* sl) {
+    // each slot has one reader, which clears it for the step after next
+    unsigned long long acc;
+    if constexpr (MAXB <= kMaxbShort) {
+      int q = t;
+      asm volatile("" : "+v"(q));
+      acc = take_slots(sl, q, T);
+      if (logT >= 1) acc += take_slots(sl + ((q & 1) ? 2 * kWave : kWave), q >> 1, T >> 1);
+    } else {
+      acc = sl[t];
+      sl[t] = 0ull;
+    }
+    const float F = FixedAcc<unsigned long long>::value_exact(acc, A.finv) + P.f_const;
+    const int r = r0 + tid;
+    F_last = F;
+    if (r < A.R) {
+      if (A.trace) A.trace[(size_t)step * A.R + r] = F;
+      if (eval) A.obj_out[r] = F;
+    }
+  };
+  // Short-constraint variants take the objective of step s off the critical
+  // path: its deposits and step s-1's finalize run at the start of step s + 1,
+  // where the dynamic work claims absorb them (a wave that spends time there
+  // claims fewer chunks).  Long-constraint variants reduce within the step.
+  constexpr bool kDefer = MAXB <= kMaxbShort;
+  ObjAcc prev{0, 0, 0};
+  int done = A.n_steps;  // steps taken (fewer once every restart has converged)
+
+  for (int s = 0; s < A.n_steps; ++s) {
+    if constexpr (kDefer) {
+      if (s > 0) {
+        deposit(prev, set_of(s - 1));
+        if (s > 1 && tid < T) finalize(s - 2, set_of(s - 2));
+      }
+    }
+    ObjAcc facc{0, 0, 0};
+    kptr<Segment> segs = kconst(P.segments);
+    for (int sg = 0; sg < n_seg; ++sg) {
+      const Segment S{segs[sg].kind,    segs[sg].bucket, segs[sg].c_begin,   segs[sg].c_count,
+                      segs[sg].lit_base, segs[sg].k_fixed, segs[sg].cls_fixed, segs[sg].m_max};
+      run_any_segment<MAXB>(P, S, xs, gs, facc, A.gsc, A.fsc, tid, logT, ctr + sg);
+    }
+    if constexpr (!kDefer) deposit(facc, set_of(0));
     __syncthreads();
     if (tid < n_seg) ctr[tid] = 0;  // every wave has left the segment loops
-    if (tid < T) {
-      // each slot has one reader, which clears it for the next step
-      unsigned long long acc;
-      if constexpr (MAXB <= kMaxbShort) {
-        int q = t;
-        asm volatile("" : "+v"(q));
-        acc = take_slots(Fl, q, T);
-        if (logT >= 1) acc += take_slots(Fl + ((q & 1) ? 2 * kWave : kWave), q >> 1, T >> 1);
-      } else {
-        acc = Fl[t];
-        Fl[t] = 0ull;
-      }
-      const float F = FixedAcc<unsigned long long>::value_exact(acc, A.finv) + P.f_const;
-      const int r = r0 + tid;
-      F_last = F;
-      if (r < A.R) {
-        if (A.trace) A.trace[(size_t)s * A.R + r] = F;
-        if (eval) A.obj_out[r] = F;
-      }
+    if constexpr (!kDefer) {
+      if (tid < T) finalize(s, set_of(0));
+    } else {
+      prev = facc;
     }
     if (eval) {
       if (A.g_out) {
@@ -1071,12 +1098,22 @@ __device__ __forceinline__ void resident_tile(const ProblemDev& P, const TileArg
       for (int q = 0; q < T; ++q) all &= conv[q];
       __syncthreads();  // flags read before the next step may change them
       if (all) {
-        if (tid < T && A.trace && r0 + tid < A.R)
-          for (int q = s + 1; q < A.n_steps; ++q) A.trace[(size_t)q * A.R + r0 + tid] = F_last;
+        done = s + 1;
         break;
       }
     }
   }
+  if constexpr (kDefer) {
+    if (done > 0) {
+      deposit(prev, set_of(done - 1));
+      if (done > 1 && tid < T) finalize(done - 2, set_of(done - 2));
+      __syncthreads();
+      if (tid < T) finalize(done - 1, set_of(done - 1));
+    }
+  }
+  // a tile that stopped early repeats its last objective for the remaining steps
+  if (tid < T && A.trace && r0 + tid < A.R)
+    for (int q = done; q < A.n_steps; ++q) A.trace[(size_t)q * A.R + r0 + tid] = F_last;
   if (!eval && A.tol > 0.f && A.iters && tid < T && r0 + tid < A.R && !conv[tid]) A.iters[r0 + tid] = A.n_steps;
   if (!eval) {
     for (int i = tid; i < NT; i += nth) {
@@ -1388,7 +1425,7 @@ int32_t device_limits(DeviceLimits& out) {
 // F[T] 64-bit, each region 8-byte aligned.
 size_t tile_lds_bytes(int n, int T, int acc_bytes) {
   const size_t nt = (size_t)n * T;
-  const size_t slots = (T >= 2 ? 3 : 1) * (size_t)kWave * 8;  // objective slots
+  const size_t slots = 2 * (T >= 2 ? 3 : 1) * (size_t)kWave * 8;  // two sets of objective slots
   return (nt * 4 + 7) / 8 * 8 + (nt * acc_bytes + 7) / 8 * 8 + slots + 4 * kMaxSegments + (size_t)T * 8;
 }
 
