@@ -141,6 +141,18 @@ int32_t pcls_upload(pcls_problem* p, void* d_workspace, size_t bytes, void* hip_
 int32_t pcls_init_restarts(const pcls_problem* p, int32_t R, uint64_t seed, float* d_x, void* hip_stream);
 
 /*
+ * Fresh starting points for selected restarts only: every restart r < R with
+ * d_mask[r] != 0 gets exactly the column pcls_init_restarts would write for
+ * this seed; all other columns of d_x (padding included) are left as they are.
+ * This is how converged restarts are recycled while the others keep running
+ * (in lockstep, restarts that have converged would otherwise idle until the
+ * slowest finishes: Case Studies, "Costas Arrays: Convergence Profile
+ * Analysis").  d_mask: device uint8 [R], read only; NULL is PCLS_E_INVALID.
+ */
+int32_t pcls_init_restarts_masked(const pcls_problem* p, int32_t R, uint64_t seed, const uint8_t* d_mask,
+                                  float* d_x, void* hip_stream);
+
+/*
  * Objective and gradient at X (Background, "Satisfaction as Optimisation").
  *   d_x    : device [n][R_pad] float32, read only.
  *   d_obj  : device [R] float32, F_r = sum_c w_c FE_c(x_r).

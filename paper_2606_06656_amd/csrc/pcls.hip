@@ -1288,10 +1288,13 @@ __device__ __forceinline__ uint32_t philox_first_word(uint32_t c0, uint32_t c1, 
   return c0;
 }
 
-__global__ void init_kernel(float* __restrict__ X, int n, int R, int ldx, uint32_t k0, uint32_t k1) {
+// mask != NULL: only restarts r < R with mask[r] != 0 are written.
+__global__ void init_kernel(float* __restrict__ X, int n, int R, int ldx, uint32_t k0, uint32_t k1,
+                            const uint8_t* __restrict__ mask) {
   const int r = blockIdx.x * blockDim.x + threadIdx.x;
   const int v = blockIdx.y;
   if (r >= ldx || v >= n) return;
+  if (mask && (r >= R || mask[r] == 0)) return;
   float x = 0.f;
   if (r < R) {
     const uint32_t o = philox_first_word((uint32_t)r, (uint32_t)v, k0, k1);
@@ -1816,7 +1819,23 @@ int32_t pcls_init_restarts(const pcls_problem* p, int32_t R, uint64_t seed, floa
   if (!d_x) return set_error(PCLS_E_INVALID, "d_x is NULL");
   const int R_pad = round_up64(R);
   hipLaunchKernelGGL(init_kernel, dim3(R_pad / 64, p->n), dim3(64), 0, (hipStream_t)stream, d_x, p->n, R, R_pad,
-                     (uint32_t)seed, (uint32_t)(seed >> 32));
+                     (uint32_t)seed, (uint32_t)(seed >> 32), (const uint8_t*)nullptr);
+  PCLS_HIP(hipGetLastError(), "init_kernel launch");
+  clear_error();
+  return PCLS_OK;
+}
+
+int32_t pcls_init_restarts_masked(const pcls_problem* p, int32_t R, uint64_t seed, const uint8_t* d_mask, float* d_x,
+                                  void* stream) {
+  int32_t st = check_bound(p);
+  if (st != PCLS_OK) return st;
+  if (R < 0) return set_error(PCLS_E_INVALID, "R must be >= 0");
+  if (R == 0) return PCLS_OK;
+  if (!d_x) return set_error(PCLS_E_INVALID, "d_x is NULL");
+  if (!d_mask) return set_error(PCLS_E_INVALID, "d_mask is NULL");
+  const int R_pad = round_up64(R);
+  hipLaunchKernelGGL(init_kernel, dim3(R_pad / 64, p->n), dim3(64), 0, (hipStream_t)stream, d_x, p->n, R, R_pad,
+                     (uint32_t)seed, (uint32_t)(seed >> 32), d_mask);
   PCLS_HIP(hipGetLastError(), "init_kernel launch");
   clear_error();
   return PCLS_OK;

@@ -22,6 +22,7 @@ STATUS_NAMES = {0: "PCLS_OK", 1: "PCLS_E_INVALID", 2: "PCLS_E_UNSUPPORTED", 3: "
 
 # exported entry points (checked by the CPU test suite against include/pcls.h)
 EXPORTS = ["pcls_plan", "pcls_plan_ex", "pcls_problem_info", "pcls_upload", "pcls_init_restarts",
+           "pcls_init_restarts_masked",
            "pcls_evaluate", "pcls_step", "pcls_step_ex", "pcls_extract", "pcls_set_launch", "pcls_launch_info",
            "pcls_destroy", "pcls_last_error",
            "pcls_batch_create", "pcls_batch_bind", "pcls_batch_set_config", "pcls_batch_get_config",
@@ -81,6 +82,8 @@ def load_library():
     L.pcls_upload.argtypes = [P, vp, sz, vp]
     L.pcls_init_restarts.restype = i32
     L.pcls_init_restarts.argtypes = [P, i32, u64, vp, vp]
+    L.pcls_init_restarts_masked.restype = i32
+    L.pcls_init_restarts_masked.argtypes = [P, i32, u64, vp, vp, vp]
     L.pcls_evaluate.restype = i32
     L.pcls_evaluate.argtypes = [P, i32, vp, vp, vp, vp]
     L.pcls_step.restype = i32
@@ -241,6 +244,18 @@ class Problem(Plan):
                                                 _stream()))
         return X
 
+    def init_restarts_masked(self, X, R: int, seed: int, mask):
+        """Redraw only the restarts r with mask[r] != 0 (uint8 or bool device
+        tensor of R entries), as init_restarts(seed) would draw them."""
+        import torch
+        self._check_state(X, R)
+        if mask.device != self.device or mask.numel() != R or mask.dtype not in (torch.uint8, torch.bool):
+            raise PclsError(PCLS_E_INVALID, "mask must be a uint8 or bool tensor of R entries on the problem's device")
+        m = mask.contiguous()
+        check(load_library().pcls_init_restarts_masked(self.handle, int(R), int(seed) & (2 ** 64 - 1), _tptr(m),
+                                                       _tptr(X), _stream()))
+        return X
+
     def evaluate(self, X, R: int, want_grad: bool = True):
         import torch
         self._check_state(X, R)
@@ -312,6 +327,38 @@ def solve(problem: Problem, R: int, steps: int, lr: float = 0.1, seed: int = 0):
     problem.step(X, R, lr, steps)
     assign, unsat, best = problem.extract(X, R)
     return X, assign, unsat, best
+
+
+def solve_recycling(problem: Problem, R: int, rounds: int, steps_per_round: int, lr: float = 0.1,
+                    tol: float = 1e-4, seed: int = 0):
+    """Convergence-aware restarts with recycling: each round runs up to
+    steps_per_round steps with the per-restart convergence test, extracts every
+    restart, and redraws the restarts that converged (seed + round) while the
+    others continue from where they are.  Returns the best assignment seen
+    (fewest violated constraints, first found), its count, and per-round
+    telemetry: restarts converged, fewest violations, mean steps taken."""
+    import numpy as np
+    import torch
+    X = problem.new_state(R)
+    problem.init_restarts(X, R, seed)
+    best_unsat, best_assign, rounds_out = None, None, []
+    for k in range(rounds):
+        _, iters = problem.step_ex(X, R, lr, steps_per_round, tol=tol, want_iters=True)
+        assign, unsat, best = problem.extract(X, R)
+        it = iters.cpu().numpy()
+        u = unsat.cpu().numpy()
+        b = int(best.cpu().numpy()[0])
+        if best_unsat is None or int(u[b]) < best_unsat:
+            best_unsat, best_assign = int(u[b]), assign[b].cpu().numpy().copy()
+        converged = it < steps_per_round
+        rounds_out.append({"round": k, "converged": int(converged.sum()), "min_unsat": int(u.min()),
+                           "mean_steps": float(it.mean())})
+        if best_unsat == 0:
+            break
+        if k + 1 < rounds and converged.any():
+            mask = torch.from_numpy(converged.astype(np.uint8)).to(problem.device)
+            problem.init_restarts_masked(X, R, seed + k + 1, mask)
+    return {"assign": best_assign, "unsat": best_unsat, "rounds": rounds_out, "state": X}
 
 
 def valu_issue_rate(blocks: int = 8192, iters: int = 2048, device="cuda:0") -> float:

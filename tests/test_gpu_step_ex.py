@@ -81,3 +81,76 @@ def test_convergence_counts_and_retirement(T):
         stop = int(first[(r // T) * T:(r // T) * T + T].max())
         if stop < S:
             assert np.all(trn[stop:, r] == trn[stop - 1, r]) or stop == 0
+
+
+def test_masked_init_redraws_only_selected_restarts():
+    """pcls_init_restarts_masked writes exactly pcls_init_restarts' columns for
+    the selected restarts (that initialiser is pinned to Philox4x32-10 against
+    the oracle) and leaves every other column, padding included, untouched."""
+    inst = synth.mixed_small(n=50, seed=3, kmax=10, count=80)
+    log("case masked init")
+    prob = pcls.Problem.from_instance(inst)
+    R = 100
+    full = prob.new_state(R)
+    prob.init_restarts(full, R, 11)
+    X = prob.new_state(R)
+    X.fill_(7.0)
+    mask = (torch.arange(R) % 3 == 0).to(torch.uint8).to(prob.device)
+    prob.init_restarts_masked(X, R, 11, mask)
+    sel = mask.bool()
+    assert torch.equal(X[:, :R][:, sel], full[:, :R][:, sel])
+    assert bool((X[:, :R][:, ~sel] == 7.0).all())
+    assert bool((X[:, R:] == 7.0).all())
+    # nothing selected: nothing changes; a second draw with another seed differs
+    before = X.clone()
+    prob.init_restarts_masked(X, R, 12, torch.zeros(R, dtype=torch.bool, device=prob.device))
+    assert torch.equal(X, before)
+    prob.init_restarts_masked(X, R, 12, mask)
+    assert not torch.equal(X[:, :R][:, sel], full[:, :R][:, sel])
+    L = pcls.load_library()
+    assert L.pcls_init_restarts_masked(prob.handle, R, 11, None, pcls._tptr(X), pcls._stream()) == pcls.PCLS_E_INVALID
+    with pytest.raises(pcls.PclsError):
+        prob.init_restarts_masked(X, R, 11, torch.ones(R + 1, dtype=torch.uint8, device=prob.device))
+
+
+def _violations(inst, a):
+    """Violated constraints of a +-1 assignment (-1 = True), counted directly
+    from the constraint definitions."""
+    bad = 0
+    for c in range(inst.m):
+        lits = inst.lit[inst.row_ptr[c]:inst.row_ptr[c + 1]]
+        y = np.sign(lits) * a[np.abs(lits) - 1]
+        t = int(np.sum(y == -1))
+        bad += 0 if C.holds(int(inst.ctype[c]), len(lits), int(inst.param[c]), t) else 1
+    return bad
+
+
+def test_recycling_rounds_redraw_converged_restarts():
+    """solve_recycling: each round's converged restarts are redrawn with seed +
+    round, the others continue; the reported best assignment has exactly the
+    reported number of violated constraints."""
+    inst = synth.random_ksat(50, 300, 3, seed=7)  # ratio 6: no restart satisfies every clause
+    log("case recycling")
+    prob = pcls.Problem.from_instance(inst)
+    R, steps, lr, tol = 96, 150, 0.1, 1e-3
+    out = pcls.solve_recycling(prob, R, rounds=3, steps_per_round=steps, lr=lr, tol=tol, seed=21)
+    assert len(out["rounds"]) == 3 and out["unsat"] > 0
+    assert out["unsat"] == min(r["min_unsat"] for r in out["rounds"])
+    assert _violations(inst, out["assign"].astype(np.int64)) == out["unsat"]
+    for r in out["rounds"]:
+        assert 0 <= r["converged"] <= R and 0 < r["mean_steps"] <= steps
+    # one round by hand: the converged restarts get seed + 1's columns, the rest
+    # keep the state they reached
+    X = prob.new_state(R)
+    prob.init_restarts(X, R, 21)
+    _, iters = prob.step_ex(X, R, lr, steps, tol=tol, want_iters=True)
+    conv = (iters < steps).to(torch.uint8)
+    log(f"rounds {out['rounds']}; converged in the round by hand: {int(conv.sum())}")
+    assert 0 < int(conv.sum()) < R  # both branches are exercised
+    after = X.clone()
+    prob.init_restarts_masked(X, R, 22, conv)
+    fresh = prob.new_state(R)
+    prob.init_restarts(fresh, R, 22)
+    c = conv.bool()
+    assert torch.equal(X[:, :R][:, c], fresh[:, :R][:, c])
+    assert torch.equal(X[:, :R][:, ~c], after[:, :R][:, ~c])
