@@ -1892,8 +1892,15 @@ int32_t pcls_extract(const pcls_problem* p, int32_t R, const float* d_x, int8_t*
   hipLaunchKernelGGL(fill_i32_kernel, dim3((R + 255) / 256), dim3(256), 0, s, d_unsat, 0, R);
   PCLS_HIP(hipGetLastError(), "fill launch");
   if (p->m > 0) {
-    const int chunk = 256;
-    hipLaunchKernelGGL(extract_count_kernel, dim3((R + 255) / 256, (p->m + chunk - 1) / chunk), dim3(256), 0, s,
+    // threads over restarts (coalesced reads of X), blocks over chunks of
+    // constraints; each thread walks its chunk serially, so the chunk is sized
+    // for about 1024 waves in total (at least 8 and at most 256 constraints),
+    // and a block is no wider than the padded restart count
+    const int threads = std::min(256, R_pad);
+    const int rblocks = (R + threads - 1) / threads;
+    const long long waves_r = (long long)rblocks * (threads / 64);
+    const int chunk = (int)std::min<long long>(256, std::max<long long>(8, (long long)p->m * waves_r / 1024));
+    hipLaunchKernelGGL(extract_count_kernel, dim3(rblocks, (p->m + chunk - 1) / chunk), dim3(threads), 0, s,
                        p->dev, d_x, R, R_pad, d_unsat, chunk);
     PCLS_HIP(hipGetLastError(), "extract_count launch");
   }
