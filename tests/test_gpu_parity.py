@@ -242,6 +242,23 @@ def test_extract_exact(seed):
     assert int(best.item()) == b_ref
 
 
+@pytest.mark.parametrize("R,count", [(1, 203), (64, 203), (300, 203), (1000, 5000)])
+def test_extract_launch_shapes(R, count):
+    """Extraction blocks follow R (narrow blocks for few restarts, several
+    restart blocks past 256) and constraint chunks follow m and R (ragged last
+    chunk here): counts, assignment and best restart stay exact."""
+    inst = synth.mixed_small(n=120, seed=R, kmax=30, count=count)
+    log(f"case extract shapes R={R} m={inst.m}")
+    prob = pcls.Problem.from_instance(inst)
+    x = corner_mix(np.random.default_rng(R), R, inst.n)
+    X = prob.state_from_rows(x)
+    assign, unsat, best = prob.extract(X, R)
+    a_ref, u_ref, b_ref = oracle_for(inst).extract(rows_of(X, R))
+    assert np.array_equal(assign.cpu().numpy(), a_ref)
+    assert np.array_equal(unsat.cpu().numpy(), u_ref)
+    assert int(best.item()) == b_ref
+
+
 def test_planted_solution_found_by_extract():
     counts = {C.OR: 40, C.XOR: 20, C.CARD_GE: 20, C.NAE: 20, C.EO: 10, C.AMO: 10, C.EK: 10}
     inst, z = synth.planted(120, counts, seed=8)
