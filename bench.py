@@ -1,17 +1,31 @@
 """Throughput benchmark of the FE objective + gradient + projected step.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c2]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c3]
 
 A step is one pass of the whole hot path over the batch: for every restart and
 every constraint, the literal gather, node products, objective, per-literal
 gradient and scatter, then the projected step of every variable.  The default
-workload is the mixed symmetric-PB instance (n = 2000 variables; 6000 random
-3-clauses, 600 XOR-5 constraints with a random parity bit, 200 "at least 3 of 8"
-cardinality constraints; 1024 restarts; float32 state), synthetic and seeded.
+workload is the largest single-GPU configuration, the long-support stress
+instance: n = 20 000 variables, 40 000 constraints with lengths drawn from a
+truncated geometric distribution on [3, 256] (mean about 12), type uniform over
+OR / XOR / at-least-ceil(k/2) / NAE with random signs, 4096 restarts, float32
+state; synthetic and seeded.
 
 Metric: literal-evaluations per second, R * L * K / t, with t the device time
-of K steps (inputs resident in HBM).  Printed as one JSON line with a roofline
-object for the dominant kernel and the oracle's CPU rate on a bounded sample.
+of K steps (inputs resident in HBM), timed with HIP events on the stream the
+library launches on.  Printed as one JSON line with
+
+- `roofline`: the binding resource of the dominant kernel, VALU issue (the
+  fraction of SIMD cycles with a vector instruction being worked on, from the
+  committed rocprofv3 counters of the same launch, over the live launch time),
+  with the measured HBM traffic of the launch;
+- `gather_model`: the throughput normalised by the algorithmic bytes of an
+  HBM-resident gather/scatter design (8 B per literal-evaluation, 8 B per
+  variable and restart, the literal stream) against the 8 TB/s HBM peak;
+- `cpu_baseline`: the FP64 oracle on a bounded sample of the same workload;
+- in the default run also the mixed instance (`c2`), the batched uneven
+  instances against per-instance launches (`c4`), and the learned versus
+  uniform restart initialisation (`learned_init`).
 """
 from __future__ import annotations
 
@@ -28,6 +42,9 @@ if ROOT not in sys.path:
 
 METRIC = "FE obj+grad literal-evals/sec (% HBM roofline); learned vs random-init sat rate"
 HBM_PEAK_GBS = 8000.0
+# VALU issue capacity: 256 CUs x 4 SIMDs, each able to work on a vector
+# instruction every cycle at 2.4 GHz (in G SIMD-cycles per second).
+VALU_PEAK_GSIMDCYC = 256 * 4 * 2.4
 PROFILE_DIR = os.path.join(ROOT, "profiles")
 KERNEL_SOURCES = ["paper_2606_06656_amd/csrc/pcls.hip", "paper_2606_06656_amd/csrc/plan.cpp",
                   "paper_2606_06656_amd/csrc/internal.h"]
@@ -48,6 +65,11 @@ def workload(name: str):
     raise SystemExit(f"unknown workload {name}")
 
 
+# steps per launch of the resident kernel: the long-support workload takes ~40 ms
+# per 10 steps, the others are short enough that 100 steps amortise the launch
+DEFAULT_STEPS_PER_LAUNCH = {"c1": 100, "c2": 100, "c3": 10, "c3long": 10}
+
+
 def algorithmic_bytes_per_step(n: int, m: int, L: int, R: int) -> int:
     """4 B x gather + 4 B gradient contribution per literal-evaluation, state read
     and write per (variable, restart), constraint literal stream and row data."""
@@ -62,57 +84,63 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-# Instruction-issue roof of the vector ALUs: 256 CUs x 4 SIMDs, one wave64
-# instruction per SIMD every 4 cycles, 2.4 GHz.
-VALU_PEAK_GINST = 256 * 4 * 2.4 / 4
-
-
-def profile_record(kernel: str, workload_key: str, kind: str, steps_per_launch: int):
-    """Per-launch figures ("traffic": HBM bytes from the FETCH_SIZE / WRITE_SIZE
-    passes scaled by the copy calibration; "counters": SQ instruction counts)
-    from a committed rocprofv3 run, if it was taken on the current kernel source
-    with the same launch size; else None."""
-    path = os.path.join(PROFILE_DIR, f"{kernel}_{workload_key}_{kind}.json")
+def profile_record(kernel: str, workload_key: str):
+    """Per-launch counter figures of the kernel from a committed rocprofv3 run on
+    the current kernel source (FETCH_SIZE / WRITE_SIZE scaled by the copy
+    calibration, SQ_ACTIVE_INST_VALU, SQ_INSTS_VALU, ...), or None."""
+    path = os.path.join(PROFILE_DIR, f"{kernel}_{workload_key}.json")
     if not os.path.exists(path):
         return None
     with open(path) as f:
         rec = json.load(f)
-    if rec.get("source_sha") != kernel_source_hash() or rec.get("steps_per_launch") != steps_per_launch:
+    if rec.get("source_sha") != kernel_source_hash():
         return None
     return rec
 
 
-def roofline(kernel: str, key: str, alg_bytes_per_launch: float, launch_ms: float, steps_per_launch: int):
-    """Gather-model HBM roofline of the dominant kernel (algorithmic bytes per
-    launch over the average launch time), with the measured HBM traffic and the
-    binding on-chip resource when committed profiles of this kernel exist."""
+def gather_model(alg_bytes_per_launch: float, launch_ms: float):
     achieved = alg_bytes_per_launch / (launch_ms / 1e3) / 1e9
-    tr = profile_record(kernel, key, "traffic", steps_per_launch)
-    out = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-           "frac": achieved / HBM_PEAK_GBS, "traffic": None if tr is None else tr["hbm_bytes_per_launch"],
-           "kernel": kernel, "launch_ms": launch_ms, "steps_per_launch": steps_per_launch,
-           "model": "gather model: 8 B per literal-eval + 8 B per (variable, restart) + CSR per step"}
-    if tr is not None:
-        # HBM rate the counters measured: the state stays in LDS, so it is far below achieved
-        out["traffic_gbs"] = tr["hbm_bytes_per_launch"] / (launch_ms / 1e3) / 1e9
-    ct = profile_record(kernel, key, "counters", steps_per_launch)
-    if ct is not None:
-        from paper_2606_06656_amd import pcls
-        rate = ct["valu_insts_per_launch"] / (launch_ms / 1e3) / 1e9
-        out["binding"] = {"bound": "alu", "resource": "VALU instruction issue", "achieved": rate,
-                          "peak": VALU_PEAK_GINST, "peak_measured": pcls.valu_issue_rate() / 1e9,
-                          "unit": "G wave64-instr/s", "frac": rate / VALU_PEAK_GINST,
-                          "valu_insts_per_launch": ct["valu_insts_per_launch"]}
+    return {"achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+            "bytes_per_launch": alg_bytes_per_launch,
+            "model": "normalisation, not HBM traffic: 8 B per literal-eval + 8 B per (variable, restart) + "
+                     "literal stream per step, the bytes an HBM-resident gather/scatter design would move; "
+                     "this engine keeps x and the gradient in LDS"}
+
+
+def roofline(kernel: str, key: str, alg_bytes_per_launch: float, launch_ms: float, steps_per_launch: int):
+    """Binding resource of the dominant kernel: VALU issue.  achieved = SIMD
+    cycles with a VALU instruction in flight per launch (SQ_ACTIVE_INST_VALU,
+    quad-cycles x 4, from the committed profile of this kernel source) over the
+    live launch time; peak = every SIMD busy every cycle.  traffic = HBM bytes
+    per launch from the FETCH_SIZE / WRITE_SIZE passes."""
+    out = {"bound": "alu", "resource": "VALU issue (SIMD cycles working on a vector instruction)",
+           "achieved": None, "peak": VALU_PEAK_GSIMDCYC, "unit": "G SIMD-cycles/s", "frac": None,
+           "traffic": None, "kernel": kernel, "launch_ms": launch_ms, "steps_per_launch": steps_per_launch}
+    rec = profile_record(kernel, key)
+    if rec is None:
+        out["note"] = "no committed profile of this kernel source: counters unavailable"
+        return out
+    scale = steps_per_launch / rec["steps_per_launch"]  # per-launch figures scale with the steps of a launch
+    busy = rec["valu_busy_quad_cycles_per_launch"] * 4 * scale
+    out["achieved"] = busy / (launch_ms / 1e3) / 1e9
+    out["frac"] = out["achieved"] / VALU_PEAK_GSIMDCYC
+    out["valu_instructions_per_launch"] = rec["valu_insts_per_launch"] * scale
+    out["valu_issue_rate_ginst"] = out["valu_instructions_per_launch"] / (launch_ms / 1e3) / 1e9
+    if rec.get("hbm_bytes_per_launch") is not None:
+        out["traffic"] = rec["hbm_bytes_per_launch"] * scale
+        hbm = out["traffic"] / (launch_ms / 1e3) / 1e9
+        out["hbm"] = {"achieved": hbm, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": hbm / HBM_PEAK_GBS}
+    if scale != 1.0:
+        out["note"] = f"counters taken at {rec['steps_per_launch']} steps per launch, scaled"
+    out["profile"] = rec.get("summary")
+    out["profile_avg_us"] = rec.get("trace_avg_us")
     return out
 
 
 def cpu_baseline(inst, lr: float, budget_s: float = 12.0, R_sample: int = 16):
     """The FP64 oracle (single-threaded C) on a bounded sample of the same
     workload: R_sample restarts, as many whole steps as fit in about budget_s."""
-    import numpy as np
-
     from oracle import native as N
-    from paper_2606_06656_amd import synth  # noqa: F401
 
     op = N.OracleProblem(inst.n, inst.row_ptr, inst.lit, inst.ctype, inst.param, inst.weight)
     x = N.init_uniform(R_sample, inst.n, 12345)
@@ -166,7 +194,72 @@ def cpu_baseline_all_cores(op, inst, lr: float, budget_s: float, R_sample: int):
             "sample": f"{P} threads x {R_sample} restarts, {steps} steps in total, {el:.1f} s"}
 
 
-def bench_batch(args, insts, R, lr, key):
+def time_resident(inst, R, lr, steps, warmup, S, tile=0, block=0):
+    """Equal launches of the resident engine, S steps each (warm-up launches of
+    the same size first), timed with HIP events on the library's stream."""
+    import torch
+
+    from paper_2606_06656_amd import pcls
+
+    prob = pcls.Problem.from_instance(inst, device="cuda:0")
+    if tile or block:
+        prob.set_launch(tile, block)
+    X = prob.new_state(R)
+    prob.init_restarts(X, R, 2)
+    stream = torch.cuda.current_stream()
+    S = max(1, min(S, steps))
+    n_launch = max(1, steps // S)
+    # every step writes each restart's objective at its iterate (obj + grad per step)
+    trace = torch.empty((S, R), dtype=torch.float32, device="cuda:0")
+    for _ in range(max(1, (warmup + S - 1) // S)):
+        prob.step(X, R, lr, S, trace=trace)
+    torch.cuda.synchronize()
+    start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    start.record(stream)
+    for _ in range(n_launch):
+        prob.step(X, R, lr, S, trace=trace)  # one launch of the resident kernel runs S steps
+    end.record(stream)
+    torch.cuda.synchronize()
+    ms = start.elapsed_time(end)
+    last = trace[-1]
+    return {"ms": ms, "steps": n_launch * S, "S": S, "n_launch": n_launch, "launch": prob.launch_info(R),
+            "objective_last_step": {"min": float(last.min()), "mean": float(last.mean())}}
+
+
+def bench_resident(name, args, with_cpu=True):
+    inst, R, lr, key = workload(name)
+    S = args.steps_per_launch or DEFAULT_STEPS_PER_LAUNCH[name]
+    t = time_resident(inst, R, lr, args.steps, args.warmup, S, args.tile, args.block)
+    ms, steps, S = t["ms"], t["steps"], t["S"]
+    value = R * inst.L * steps / (ms / 1e3)
+    alg = algorithmic_bytes_per_step(inst.n, inst.m, inst.L, R) * S
+    out = {
+        "metric": METRIC, "value": value, "unit": "literal-evals/s", "n_gpus": 1, "steps": steps,
+        "warmup": args.warmup, "ms_per_step": ms / steps, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": key, "n": inst.n, "m": inst.m, "L": inst.L, "restarts": R, "lr": lr,
+                   "steps_per_launch": S, "launch": t["launch"]},
+        "objective_last_step": t["objective_last_step"],
+        "roofline": roofline("tile_kernel", key, alg, ms / t["n_launch"], S),
+        "gather_model": gather_model(alg, ms / t["n_launch"]),
+    }
+    if with_cpu and not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(inst, lr, args.cpu_budget)
+    return out
+
+
+def bench_c2_extra(args):
+    """The mixed n = 2000 instance (1024 restarts, 100 steps per launch)."""
+    inst, R, lr, key = workload("c2")
+    t = time_resident(inst, R, lr, 200, 100, 100)
+    value = R * inst.L * t["steps"] / (t["ms"] / 1e3)
+    alg = algorithmic_bytes_per_step(inst.n, inst.m, inst.L, R) * t["S"]
+    return {"workload": key, "value": value, "unit": "literal-evals/s", "steps": t["steps"],
+            "ms_per_step": t["ms"] / t["steps"], "launch": t["launch"],
+            "gather_model": gather_model(alg, t["ms"] / t["n_launch"])}
+
+
+def bench_batch(args, insts, R, lr, key, steps=None, warmup=None):
     """Many uneven instances: one persistent launch per captured graph replay
     (configuration from the autotuner) against per-instance plain launches."""
     import torch
@@ -174,21 +267,23 @@ def bench_batch(args, insts, R, lr, key):
     from paper_2606_06656_amd import pcls
     from paper_2606_06656_amd.batch import Batch
 
+    steps = args.steps if steps is None else steps
+    warmup = args.warmup if warmup is None else warmup
     probs = [pcls.Problem.from_instance(i, device="cuda:0") for i in insts]
     states = []
     for k, p in enumerate(probs):
         X = p.new_state(R)
         p.init_restarts(X, R, 4000 + k)
         states.append(X)
-    S = args.graph_steps
+    S = max(1, min(args.graph_steps, steps))
     # every step writes each restart's objective (obj + grad per step)
     traces = [torch.empty((S, R), dtype=torch.float32, device="cuda:0") for _ in probs]
     b = Batch(probs, [R] * len(probs), states, traces)
     tune = b.autotune(lr, probe_steps=3, cache_path=args.tune_cache)
-    reps = max(1, args.steps // S)
+    reps = max(1, steps // S)
     steps = reps * S
     b.capture(lr, S)
-    for _ in range(max(1, args.warmup // S)):
+    for _ in range(max(1, warmup // S)):
         b.replay()
     torch.cuda.synchronize()
     stream = torch.cuda.current_stream()
@@ -200,8 +295,6 @@ def bench_batch(args, insts, R, lr, key):
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1)
     L_tot = sum(i.L for i in insts)
-    n_tot = sum(i.n for i in insts)
-    m_tot = sum(i.m for i in insts)
     value = R * L_tot * steps / (ms / 1e3)
     # per-instance plain launches: one pcls_step(1) per instance per step
     bs = args.baseline_steps
@@ -214,57 +307,87 @@ def bench_batch(args, insts, R, lr, key):
     ms_b = e0.elapsed_time(e1)
     base_rate = R * L_tot * bs / (ms_b / 1e3)
     alg = sum(algorithmic_bytes_per_step(i.n, i.m, i.L, R) for i in insts) * S
-    cfg = b.config()
+    return {"value": value, "ms": ms, "steps": steps, "S": S, "reps": reps, "L_tot": L_tot,
+            "n_tot": sum(i.n for i in insts), "m_tot": sum(i.m for i in insts), "tune": tune, "cfg": b.config(),
+            "per_instance_launches": {"value": base_rate, "unit": "literal-evals/s", "steps": bs,
+                                      "ms_per_step": ms_b / bs, "launches_per_step": len(insts),
+                                      "speedup_of_batched": value / base_rate},
+            "alg": alg}
+
+
+def bench_c4_line(args):
+    insts, R, lr, key = workload("c4")
+    r = bench_batch(args, insts, R, lr, key)
     out = {
-        "metric": METRIC, "value": value, "unit": "literal-evals/s", "n_gpus": 1, "steps": steps,
-        "warmup": args.warmup, "ms_per_step": ms / steps, "higher_is_better": True, "scaling": "weak",
+        "metric": METRIC, "value": r["value"], "unit": "literal-evals/s", "n_gpus": 1, "steps": r["steps"],
+        "warmup": args.warmup, "ms_per_step": r["ms"] / r["steps"], "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-        "config": {"workload": key, "instances": len(insts), "sum_n": n_tot, "sum_m": m_tot, "sum_L": L_tot,
-                   "restarts_each": R, "lr": lr, "graph_steps": S, "autotune": tune, "batch": cfg},
-        "per_instance_launches": {"value": base_rate, "unit": "literal-evals/s", "steps": bs,
-                                  "ms_per_step": ms_b / bs, "launches_per_step": len(insts),
-                                  "speedup_of_batched": value / base_rate},
-        "roofline": roofline("batch_kernel", key, alg, ms / reps, S),
+        "config": {"workload": key, "instances": len(insts), "sum_n": r["n_tot"], "sum_m": r["m_tot"],
+                   "sum_L": r["L_tot"], "restarts_each": R, "lr": lr, "graph_steps": r["S"],
+                   "autotune": r["tune"], "batch": r["cfg"]},
+        "per_instance_launches": r["per_instance_launches"],
+        "roofline": roofline("batch_kernel", key, r["alg"], r["ms"] / r["reps"], r["S"]),
+        "gather_model": gather_model(r["alg"], r["ms"] / r["reps"]),
     }
     print(json.dumps(out), flush=True)
+
+
+def bench_c4_extra(args):
+    insts, R, lr, key = workload("c4")
+    r = bench_batch(args, insts, R, lr, key, steps=100, warmup=50)
+    return {"workload": key, "value": r["value"], "unit": "literal-evals/s", "steps": r["steps"],
+            "ms_per_step": r["ms"] / r["steps"], "graph_steps": r["S"], "autotune": r["tune"], "batch": r["cfg"],
+            "per_instance_launches": r["per_instance_launches"],
+            "gather_model": gather_model(r["alg"], r["ms"] / r["reps"])}
 
 
 WEIGHTS = os.path.join(ROOT, "paper_2606_06656_amd", "weights", "mpnn_3sat.npz")
 
 
-def learned_vs_random(count=16, n=200, budgets=(0, 10, 50), R=64):
+def learned_vs_random(count=8, sizes=(200, 1000, 2000), budgets=(0, 10, 50, 200), R=64):
     """Second half of the metric: satisfied-constraint fraction of learned versus
     uniform restarts at equal step budgets on held-out random 3-SAT (ratio 4.2),
-    using the committed network weights; None if no weights are committed."""
+    mean over restarts and best of the restarts, each with the paired per-instance
+    difference and its 95% bootstrap interval; None if no weights are committed."""
     if not os.path.exists(WEIGHTS):
         return None
     from paper_2606_06656_amd import learned as LRN
     from paper_2606_06656_amd import synth
     P, meta = LRN.Params.load(WEIGHTS, "cuda:0")
-    insts = [synth.c5_eval(n, i) for i in range(count)]
-    lrn = LRN.sat_fraction_curves(insts, list(budgets), R=R, seed=20000, P=P, gamma=meta["gamma"],
-                                  sigma=meta["sigma"])
-    uni = LRN.sat_fraction_curves(insts, list(budgets), R=R, seed=20000, P=None)
-    rows = []
-    for bi, S in enumerate(budgets):
-        d = lrn["mean"][:, bi] - uni["mean"][:, bi]
-        m, lo, hi = LRN.paired_bootstrap_ci(d, seed=S)
-        rows.append({"steps": S, "sat_rate_learned": float(lrn["mean"][:, bi].mean()),
-                     "sat_rate_random": float(uni["mean"][:, bi].mean()), "gain": m, "gain_ci95": [lo, hi],
-                     "best_of_R_learned": float(lrn["best"][:, bi].mean()),
-                     "best_of_R_random": float(uni["best"][:, bi].mean())})
-    return {"instances": count, "n": n, "ratio": 4.2, "restarts": R, "statistic": "mean over restarts",
-            "budgets": rows}
+    per_size = []
+    for n in sizes:
+        insts = [synth.c5_eval(n, i) for i in range(count)]
+        lrn = LRN.sat_fraction_curves(insts, list(budgets), R=R, seed=20000, P=P, gamma=meta["gamma"],
+                                      sigma=meta["sigma"])
+        uni = LRN.sat_fraction_curves(insts, list(budgets), R=R, seed=20000, P=None)
+        rows = []
+        for bi, S in enumerate(budgets):
+            row = {"steps": S}
+            for stat in ("mean", "best"):
+                d = lrn[stat][:, bi] - uni[stat][:, bi]
+                m, lo, hi = LRN.paired_bootstrap_ci(d, seed=S + n)
+                row[stat] = {"learned": float(lrn[stat][:, bi].mean()), "random": float(uni[stat][:, bi].mean()),
+                             "gain": m, "gain_ci95": [lo, hi]}
+            rows.append(row)
+        per_size.append({"n": n, "m": int(round(4.2 * n)), "budgets": rows})
+    # what the intervals say about best-of-R at the larger budgets
+    flat = [(s["n"], r["steps"], r["best"]["gain_ci95"]) for s in per_size for r in s["budgets"] if r["steps"] >= 50]
+    no_gain = [f"n={n} S={S}" for n, S, ci in flat if ci[0] <= 0.0]
+    finding = ("best-of-R gain is significant at every budget >= 50" if not no_gain else
+               "best-of-R shows no significant gain (95% interval reaches 0) at " + ", ".join(no_gain) +
+               "; the learned start's advantage is in the mean over restarts and fades with the step budget")
+    return {"instances_per_size": count, "ratio": 4.2, "restarts": R, "sizes": per_size, "finding": finding}
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=1000)
-    ap.add_argument("--warmup", type=int, default=100)
-    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c3long", "c4"])
-    ap.add_argument("--steps-per-launch", type=int, default=100,
-                    help="steps per launch of the resident kernel (timed and warm-up launches alike)")
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--workload", default="c3", choices=["c1", "c2", "c3", "c3long", "c4"])
+    ap.add_argument("--steps-per-launch", type=int, default=0,
+                    help="steps per launch of the resident kernel, timed and warm-up launches alike "
+                         "(0 = 10 for c3 / c3long, 100 otherwise)")
     ap.add_argument("--graph-steps", type=int, default=50, help="c4: steps captured per graph replay")
     ap.add_argument("--tune-cache", default=None, help="c4: autotuner cache file (reused when present)")
     ap.add_argument("--baseline-steps", type=int, default=10, help="c4: steps of per-instance plain launches")
@@ -272,10 +395,17 @@ def main():
     ap.add_argument("--block", type=int, default=0, help="threads per workgroup (0 = auto)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=12.0)
-    ap.add_argument("--no-learned", action="store_true", help="skip the learned-vs-random restart comparison")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="headline workload only (no c2 / c4 / learned-initialisation sections)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run 5 device copies of MIB MiB (scales the HBM byte counters)")
     args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported: this build runs on one GPU "
+              "(restarts are independent, so several GPUs would each run their own share with no per-step "
+              "exchange).", file=sys.stderr)
+        sys.exit(2)
 
     if args.copy_calibration:
         import torch
@@ -288,66 +418,12 @@ def main():
         print(json.dumps({"copy_calibration_bytes": n * 4, "copies": 5}), flush=True)
         return
 
-    if args.gpus != 1:
-        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (restarts are independent, "
-              "so several GPUs would each run their own share with no per-step exchange).", file=sys.stderr)
-        sys.exit(2)
-
-    import torch
-
-    from paper_2606_06656_amd import pcls
-
-    inst, R, lr, key = workload(args.workload)
     if args.workload == "c4":
-        return bench_batch(args, inst, R, lr, key)
-    prob = pcls.Problem.from_instance(inst, device="cuda:0")
-    if args.tile or args.block:
-        prob.set_launch(args.tile, args.block)
-    X = prob.new_state(R)
-    prob.init_restarts(X, R, 2)
-    stream = torch.cuda.current_stream()
-    S = max(1, min(args.steps_per_launch, args.steps))
-    n_launch = max(1, args.steps // S)
-    steps = n_launch * S
-    # every step writes each restart's objective at its iterate (obj + grad per step)
-    trace = torch.empty((S, R), dtype=torch.float32, device="cuda:0")
-    for _ in range((args.warmup + S - 1) // S):
-        prob.step(X, R, lr, S, trace=trace)
-    torch.cuda.synchronize()
-
-    start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    start.record(stream)
-    for _ in range(n_launch):
-        prob.step(X, R, lr, S, trace=trace)  # one launch of the resident kernel runs S steps
-    end.record(stream)
-    torch.cuda.synchronize()
-    ms = start.elapsed_time(end)
-    t = ms / 1e3
-
-    value = R * inst.L * steps / t
-    last_obj = trace[-1]
-    out = {
-        "metric": METRIC,
-        "value": value,
-        "unit": "literal-evals/s",
-        "n_gpus": 1,
-        "steps": steps,
-        "warmup": args.warmup,
-        "ms_per_step": ms / steps,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f32",
-        "data": "synthetic",
-        "config": {"workload": key, "n": inst.n, "m": inst.m, "L": inst.L, "restarts": R, "lr": lr,
-                   "launch": prob.launch_info(R)},
-        "objective_last_step": {"min": float(last_obj.min()), "mean": float(last_obj.mean())},
-        "roofline": roofline("tile_kernel", key, algorithmic_bytes_per_step(inst.n, inst.m, inst.L, R) * S,
-                             ms / n_launch, S),
-    }
-    if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(inst, lr, args.cpu_budget)
-    if args.workload == "c2" and not args.no_learned:
+        return bench_c4_line(args)
+    out = bench_resident(args.workload, args)
+    if args.workload == "c3" and not args.no_extras:
+        out["c2"] = bench_c2_extra(args)
+        out["c4"] = bench_c4_extra(args)
         out["learned_init"] = learned_vs_random()
     print(json.dumps(out), flush=True)
 

@@ -126,7 +126,14 @@ int32_t pcls_problem_info(const pcls_problem* p, pcls_info* info);
 /*
  * Copy the plan into caller-owned device memory d_workspace (>= workspace_bytes,
  * 256-byte aligned), asynchronously on stream, and bind it to the plan.  The
- * workspace must stay allocated while the plan is used.
+ * image holds what the evaluation of every constraint needs (paper: Background,
+ * "Walsh-Fourier Transformation", eq. wfcoef and the DFT evaluation named in
+ * "Satisfaction as Optimisation"): the spectra sp_i, the inverse-DFT node
+ * weights and node factors planned from them, and the constraints' literals in
+ * segment order.  The workspace must stay allocated while the plan is used;
+ * the library never frees it.  Errors: PCLS_E_INVALID for a NULL plan;
+ * PCLS_E_WORKSPACE for a NULL or not 256-byte aligned workspace or when
+ * bytes < workspace_bytes; PCLS_E_HIP when the copy cannot be enqueued.
  */
 int32_t pcls_upload(pcls_problem* p, void* d_workspace, size_t bytes, void* hip_stream);
 
@@ -194,7 +201,10 @@ int32_t pcls_step_ex(const pcls_problem* p, int32_t R, float* d_x, float lr, int
                      const pcls_step_options* options, void* hip_stream);
 
 /*
- * Round X to corners and count violated constraints exactly.
+ * Round X to corners and count violated constraints exactly (paper: Background,
+ * "Satisfaction as Optimisation": a corner sign(X) satisfies the formula iff
+ * sum_c FE_c(sign X) = -m, i.e. iff every constraint's spectrum entry sp_i at
+ * its number i of true literals is -1, eq. wfcoef).
  *   d_assign : device [R][n] int8 or NULL; -1 (True) where x < 0, else +1
  *              (False; -0.0 and +0.0 both give False).
  *   d_unsat  : device [R] int32, number of constraints violated by the corner.
@@ -301,15 +311,6 @@ int32_t pcls_constraint_grad_stats(const pcls_problem* p, int32_t R, const float
 /* Thread-local description of the last error; valid until the next call. */
 const char* pcls_last_error(void);
 
-/*
- * Measurement utility (not part of the method): launches `blocks` workgroups of
- * 256 threads, each lane running iters x 64 fused multiply-adds in eight
- * independent chains with no memory traffic, then one store per lane to
- * d_out[blocks * 256] (device, caller-owned).  Timing it gives the VALU
- * instruction-issue ceiling: blocks * 4 * iters * 64 wave64 instructions.
- * Asynchronous on `stream`; PCLS_E_INVALID for a non-positive size or NULL.
- */
-int32_t pcls_valu_probe(int32_t blocks, int32_t iters, float* d_out, void* stream);
 
 #ifdef __cplusplus
 }

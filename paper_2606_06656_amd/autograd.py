@@ -3,9 +3,14 @@
 `FEObjective.apply(x, problem)` maps restart rows x (R, n) float32 on the GPU to
 F(x) (R,) = sum_c w_c FE_c(x_r) (Background, "Satisfaction as Optimisation").
 The forward pass runs the library's evaluation kernel, which produces the
-gradient in the same pass; backward returns grad_F[:, None] * dF/dx.  The
-objective is the multilinear polynomial itself, so it is defined (and
-differentiated) for any real x, not only on [-1, 1]^n.
+gradient in the same pass; backward returns grad_F[:, None] * dF/dx.
+
+The relaxation is defined on the cube Q^n = [-1, 1]^n, and the library's exact
+fixed-point accumulation is scaled for it: every objective and gradient term is
+bounded by its constraint's weight there, but outside the cube the products
+prod_i (1 +- x_i)/2 grow geometrically with the constraint length and the
+fixed-point sums would overflow.  forward() therefore rejects any entry with
+|x| > 1 (or NaN) with a ValueError instead of returning a wrong value.
 """
 from __future__ import annotations
 
@@ -21,6 +26,9 @@ class FEObjective(torch.autograd.Function):
             raise ValueError(f"x must be (R, {problem.n}), got {tuple(x.shape)}")
         if x.device != problem.device:
             raise ValueError("x must live on the problem's device")
+        if not bool(torch.all(x.detach().abs() <= 1)):
+            raise ValueError("x must lie in [-1, 1]^n (the cube the objective and its fixed-point scales are "
+                             "defined on)")
         R = x.shape[0]
         X = problem.new_state(R)
         X[:, :R] = x.detach().to(torch.float32).T

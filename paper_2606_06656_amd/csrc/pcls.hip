@@ -1246,24 +1246,6 @@ __global__ void __launch_bounds__(1024) batch_kernel(const BatchInst* __restrict
   }
 }
 
-// Measurement utility: eight independent FMA chains per lane, no memory
-// traffic in the loop, so the launch runs at the VALU instruction-issue ceiling.
-__global__ void __launch_bounds__(256) valu_probe_kernel(float* __restrict__ out, int iters, float a, float b) {
-  float x[8];
-#pragma unroll
-  for (int u = 0; u < 8; ++u) x[u] = (float)(threadIdx.x + u);
-  for (int i = 0; i < iters; ++i) {
-#pragma unroll
-    for (int r = 0; r < 8; ++r)
-#pragma unroll
-      for (int u = 0; u < 8; ++u) x[u] = fmaf(x[u], a, b);
-  }
-  float acc = 0.f;
-#pragma unroll
-  for (int u = 0; u < 8; ++u) acc += x[u];
-  out[(size_t)blockIdx.x * blockDim.x + threadIdx.x] = acc;
-}
-
 __global__ void fill_u32_kernel(unsigned int* p, unsigned int v, int count) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < count) p[i] = v;
@@ -2162,14 +2144,5 @@ int32_t pcls_destroy(pcls_problem* p) {
 }
 
 const char* pcls_last_error(void) { return pcls::last_error(); }
-
-int32_t pcls_valu_probe(int32_t blocks, int32_t iters, float* d_out, void* stream) {
-  if (blocks < 1 || iters < 1 || !d_out) return set_error(PCLS_E_INVALID, "blocks, iters >= 1 and d_out required");
-  hipLaunchKernelGGL(valu_probe_kernel, dim3(blocks), dim3(256), 0, (hipStream_t)stream, d_out, iters, 0.999f,
-                     0.001f);
-  PCLS_HIP(hipGetLastError(), "valu_probe_kernel launch");
-  clear_error();
-  return PCLS_OK;
-}
 
 }  // extern "C"

@@ -27,7 +27,7 @@ EXPORTS = ["pcls_plan", "pcls_plan_ex", "pcls_problem_info", "pcls_upload", "pcl
            "pcls_destroy", "pcls_last_error",
            "pcls_batch_create", "pcls_batch_bind", "pcls_batch_set_config", "pcls_batch_get_config",
            "pcls_batch_step", "pcls_batch_capture", "pcls_batch_replay", "pcls_batch_autotune",
-           "pcls_batch_destroy", "pcls_valu_probe", "pcls_constraint_grad_stats"]
+           "pcls_batch_destroy", "pcls_constraint_grad_stats"]
 
 
 class PclsError(RuntimeError):
@@ -101,8 +101,6 @@ def load_library():
     L.pcls_destroy.argtypes = [P]
     L.pcls_last_error.restype = ctypes.c_char_p
     L.pcls_last_error.argtypes = []
-    L.pcls_valu_probe.restype = i32
-    L.pcls_valu_probe.argtypes = [i32, i32, vp, vp]
     L.pcls_constraint_grad_stats.restype = i32
     L.pcls_constraint_grad_stats.argtypes = [P, i32, vp, vp, vp, vp]
     _lib = L
@@ -359,19 +357,3 @@ def solve_recycling(problem: Problem, R: int, rounds: int, steps_per_round: int,
             mask = torch.from_numpy(converged.astype(np.uint8)).to(problem.device)
             problem.init_restarts_masked(X, R, seed + k + 1, mask)
     return {"assign": best_assign, "unsat": best_unsat, "rounds": rounds_out, "state": X}
-
-
-def valu_issue_rate(blocks: int = 8192, iters: int = 2048, device="cuda:0") -> float:
-    """Measured VALU instruction-issue ceiling of the device, in wave64
-    instructions per second (timed launch of pcls_valu_probe after a warm-up)."""
-    import torch
-    out = torch.empty(blocks * 256, dtype=torch.float32, device=device)
-    L = load_library()
-    st = _stream()
-    check(L.pcls_valu_probe(blocks, iters, _tptr(out), st))
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record()
-    check(L.pcls_valu_probe(blocks, iters, _tptr(out), st))
-    e1.record()
-    torch.cuda.synchronize()
-    return blocks * 4 * iters * 64 / (e0.elapsed_time(e1) / 1e3)

@@ -25,7 +25,9 @@ def test_backward_matches_central_differences(h):
     log(f"case autograd fd h={h}")
     R = 8
     rng = np.random.default_rng(4)
-    x = torch.tensor(rng.uniform(-0.8, 0.8, (R, inst.n)), dtype=torch.float32, device=prob.device,
+    # points whose shifted copies x +- h stay inside the cube
+    a = 1.0 - h
+    x = torch.tensor(rng.uniform(-a, a, (R, inst.n)), dtype=torch.float32, device=prob.device,
                      requires_grad=True)
     F = fe_objective(prob, x)
     gF = torch.tensor(rng.uniform(0.5, 1.5, R), dtype=torch.float32, device=prob.device)
@@ -90,3 +92,12 @@ def test_no_grad_path_and_shape_errors():
     assert F.shape == (5,)
     with pytest.raises(ValueError):
         fe_objective(prob, torch.zeros((5, inst.n + 1), device=prob.device))
+    # outside the cube (or NaN) the fixed-point scales do not hold: refused, not evaluated
+    for bad in (1.0 + 2.0 ** -20, -3.0, float("nan")):
+        xb = torch.zeros((5, inst.n), device=prob.device)
+        xb[2, 7] = bad
+        with pytest.raises(ValueError):
+            fe_objective(prob, xb)
+    # the faces of the cube are inside
+    F = fe_objective(prob, torch.ones((5, inst.n), device=prob.device))
+    assert torch.isfinite(F).all()

@@ -348,20 +348,6 @@ def test_accumulator_widths(bits):
     assert torch.isfinite(Xs).all()
 
 
-def test_valu_probe_measures_issue_rate():
-    """The measurement utility behind bench.py's VALU roof: runs, writes every
-    lane, and reports a rate of the right order (hundreds of G wave64-instr/s)."""
-    log("case valu probe")
-    out = torch.full((64 * 256,), float("nan"), device="cuda:0")
-    L = pcls.load_library()
-    pcls.check(L.pcls_valu_probe(64, 16, pcls._tptr(out), pcls._stream()))
-    torch.cuda.synchronize()
-    assert torch.isfinite(out).all()
-    rate = pcls.valu_issue_rate(blocks=2048, iters=256)
-    assert 5e10 < rate < 5e12, rate
-    assert L.pcls_valu_probe(0, 16, pcls._tptr(out), pcls._stream()) == pcls.PCLS_E_INVALID
-
-
 @pytest.mark.parametrize("T", [2, 4, 8])
 def test_short_types_two_restart_lanes(T):
     """Every type with k <= 8 (products, two-node products, count windows, DFT)

@@ -311,14 +311,79 @@ def test_weights_scale_terms():
     assert one["obj"][0] != pytest.approx(wt["obj"][0])
 
 
-def test_step_is_clamped_descent():
-    rng = np.random.default_rng(10)
-    x = rng.uniform(-1, 1, 1000)
-    g = rng.normal(0, 5, 1000)
-    out = N.step(x, g, 0.1)
-    ref = np.minimum(1.0, np.maximum(-1.0, x - 0.1 * g))
-    assert np.array_equal(out, ref)
-    assert np.all(np.abs(out) <= 1.0)
+def exact_problem_step(inst, x, lr):
+    """One projected gradient step of a whole problem in exact rationals, built
+    from definitions only: the gradient of the objective is the sum over
+    constraints of the exact multilinear differences (FE|y_i=1 - FE|y_i=-1)/2
+    of the exact expectation, times the literal sign (y = s x); the projection
+    onto [-1, 1]^n is the nearest point of the box, found per coordinate by
+    comparing distances to the candidates {-1, 1, x - lr g} that lie in the
+    box ("Satisfaction as Optimisation": projected gradient descent on the cube)."""
+    n = inst.n
+    g = [Fraction(0)] * n
+    for c in range(inst.m):
+        b, e = int(inst.row_ptr[c]), int(inst.row_ptr[c + 1])
+        sp = C.spectrum(int(inst.ctype[c]), e - b, int(inst.param[c]))
+        sgn = [1 if inst.lit[i] > 0 else -1 for i in range(b, e)]
+        var = [abs(int(inst.lit[i])) - 1 for i in range(b, e)]
+        y = [sgn[j] * x[var[j]] for j in range(e - b)]
+        for j in range(e - b):
+            hi = exact_expectation(sp, y[:j] + [1.0] + y[j + 1:])
+            lo = exact_expectation(sp, y[:j] + [-1.0] + y[j + 1:])
+            g[var[j]] += sgn[j] * (hi - lo) / 2
+    out = []
+    lrq = Fraction(lr)
+    for v in range(n):
+        target = Fraction(float(x[v])) - lrq * g[v]
+        cands = [Fraction(-1), Fraction(1)] + ([target] if -1 <= target <= 1 else [])
+        out.append(min(cands, key=lambda z: abs(z - target)))
+    return g, out
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_step_equals_exact_projected_step(seed):
+    """orc_step after the oracle's evaluation equals the exact-rational projected
+    step bit for bit: every input is dyadic with few bits (x multiples of 2^-6,
+    lr = 2 or 1/4), so the exact result is representable in FP64 and any slip
+    in sign, step size or clamp shows.  lr = 2 drives many coordinates past +1
+    and -1, so both clamp faces are exercised."""
+    rng = np.random.default_rng(seed)
+    inst = synth.mixed_small(n=8, seed=seed, kmax=5, count=7)
+    op = N.OracleProblem(inst.n, inst.row_ptr, inst.lit, inst.ctype, inst.param, inst.weight)
+    for lr in (2.0, 0.25):
+        x = rng.integers(-64, 65, inst.n) / 64.0
+        g_exact, want = exact_problem_step(inst, list(x), lr)
+        res = op.evaluate(x[None, :], method=N.AUTO)
+        got = N.step(x[None, :], res["grad"], lr)[0]
+        assert [Fraction(float(v)) for v in got] == want, (lr, got, [float(w) for w in want])
+        if lr == 2.0:
+            assert any(w == 1 for w in want) and any(w == -1 for w in want)
+        # the step moves against the gradient wherever it is not clamped
+        for v in range(inst.n):
+            if -1 < want[v] < 1 and g_exact[v] != 0:
+                assert (want[v] - Fraction(float(x[v]))) * g_exact[v] < 0
+
+
+def test_step_single_clause_closed_form():
+    """OR-3 clause (Appendix A: FE = -1 + 2^(1-k) prod(1 + y_i)) at a dyadic point:
+    the clamped update written from the closed form's derivative, in exact
+    rationals, against orc_step on the oracle's own gradient."""
+    inst = synth.Instance(n=4, row_ptr=np.array([0, 3], np.int32), lit=np.array([1, -3, 4], np.int32),
+                          ctype=np.array([C.OR], np.int8), param=np.array([0], np.int32))
+    x = np.array([0.5, 0.25, -0.75, 0.875])
+    y = [Fraction(1, 2), Fraction(3, 4), Fraction(7, 8)]  # y = s x for literals +1, -3, +4
+    sgn = {0: 1, 2: -1, 3: 1}
+    prod_others = {0: (1 + y[1]) * (1 + y[2]), 2: (1 + y[0]) * (1 + y[2]), 3: (1 + y[0]) * (1 + y[1])}
+    op = N.OracleProblem(inst.n, inst.row_ptr, inst.lit, inst.ctype, inst.param)
+    res = op.evaluate(x[None, :], method=N.ESP)
+    for lr in (Fraction(1, 8), Fraction(8)):
+        got = N.step(x[None, :], res["grad"], float(lr))[0]
+        for v in range(4):
+            gv = sgn[v] * Fraction(1, 4) * prod_others[v] if v in sgn else Fraction(0)
+            want = min(Fraction(1), max(Fraction(-1), Fraction(float(x[v])) - lr * gv))
+            assert Fraction(float(got[v])) == want, (lr, v)
+    # lr = 8 pushes x_1 (positive literal, gradient > 0) to -1 and x_3 (negated) to +1
+    assert got[0] == -1.0 and got[2] == 1.0 and got[1] == 0.25
 
 
 def test_extract_sign_convention():
