@@ -17,16 +17,18 @@ namespace pcls {
 //   PROD2 - two real nodes (sp constant on 1..k-1):
 //           FE = c0 + c1 * prod_i (1+y_i)/2 + c2 * prod_i (1-y_i)/2
 //   DFT   - the K = k+1 complex roots of unity: FE = sum_m chat_m prod_i(alpha_m + beta_m y_i)
-//   PMF   - k <= 8 and sp constant outside a window of at most 4 counts at one
-//           end (thresholds, at-most-one, exactly-kappa near an end): with C the
-//           number of true literals (or of false ones),
-//           FE = c0 + sum_{c < 4} d_c Pr[C = c], from a truncated Poisson-binomial
+//   PMF   - sp constant outside a window of w counts at one end (thresholds,
+//           at-most-one, exactly-kappa near an end), w <= 4 for k <= 8 (one lane
+//           per pair) and w <= KMAX/2 of the length bucket for 8 < k <= 32 (lane
+//           groups): with C the number of true literals (or of false ones),
+//           FE = c0 + sum_{c < w} d_c Pr[C = c], from a truncated Poisson-binomial
 //           recursion and its adjoint (no products of complex factors)
 //   CONST - sp constant: FE = c0, no literal work
 enum Kind : int32_t { KIND_PROD1 = 0, KIND_PROD2 = 1, KIND_DFT = 2, KIND_PMF = 3, KIND_CONST = 4 };
 constexpr int kNumKinds = 5;
-constexpr int kPmfWindow = 4;  // counts kept by the PMF kind
-constexpr int kPmfMaxK = 8;    // longest constraint of the PMF kind (one lane per pair)
+constexpr int kPmfWindow = 4;  // counts kept by the PMF kind, one lane per pair (k <= 8)
+constexpr int kPmfMaxK = 8;    // longest constraint of the one-lane PMF kind
+constexpr int kPmfGroupMaxK = 32;  // longest constraint of the lane-group PMF kind (window <= bucket / 2)
 
 // Length buckets of the segment kernels: literals per constraint padded to KMAX,
 // processed by groups of G lanes holding J = KMAX / G literals each.
@@ -40,7 +42,7 @@ constexpr int kMaxK = 256;
 constexpr int kMaxSegments = 4 * kNumBuckets;  // (kind, bucket) pairs of the non-constant kinds
 
 // Lanes per (constraint, restart) pair: one lane holds up to 16 literals of a
-// product kind or 8 of the DFT kind (register budget at 4 waves per SIMD);
+// product kind or 8 of the DFT and PMF kinds (register budget at 4 waves per SIMD);
 // longer constraints spread over G lanes (a power of two) of at most 8 literals
 // each (6 for the buckets 12, 24, ..., 192).
 constexpr int lane_groups(int kmax) {
@@ -49,7 +51,7 @@ constexpr int lane_groups(int kmax) {
   return g;
 }
 constexpr int group_size(int kind, int kmax) {
-  return kind == KIND_PMF ? 1 : (kmax <= 8 || (kind != KIND_DFT && kmax <= 16)) ? 1 : lane_groups(kmax);
+  return (kmax <= 8 || (kind != KIND_DFT && kind != KIND_PMF && kmax <= 16)) ? 1 : lane_groups(kmax);
 }
 
 inline int bucket_of(int k) {
@@ -85,8 +87,10 @@ struct ClassRec {
 
 // DFT node m of a class: factor alpha + beta y, weight 2*chat_m for the value
 // and 2*chat_m*beta_m for the gradient (the 2 covers the conjugate node K - m).
-// A PMF class has one record: {d_0, d_1, d_2, d_3, h, 0, 0, 0}, where the counted
-// event of literal i has probability 1/2 - h y_i (h = 1/2: true, -1/2: false).
+// A PMF class of k <= 8 literals has one record: {d_0, d_1, d_2, d_3, h, 0, 0, 0},
+// where the counted event of literal i has probability 1/2 - h y_i (h = 1/2:
+// true, -1/2: false); a longer one has three records read as 24 floats:
+// d_0..d_15 (zero past its window), h, then padding.
 struct NodeRec {
   float ar, ai, br, bi;
   float wr, wi, gr, gi;

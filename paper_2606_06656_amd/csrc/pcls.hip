@@ -535,6 +535,144 @@ __device__ __forceinline__ void pmf_pair(const ProblemDev& P, int cls, const Fet
   }
 }
 
+// Lane exchange inside a pair's lane group: the value of the lane at xor
+// distance dist.  Distances 1 and 2 are DPP quad permutations (one VALU move,
+// no LDS traffic); longer ones are wave shuffles.
+template <int N>
+__device__ __forceinline__ void xor_exchange(const float (&src)[N], float (&dst)[N], int dist) {
+  if (dist == 1) {
+#pragma unroll
+    for (int i = 0; i < N; ++i) dst[i] = __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(src[i]), 0xB1, 0xf, 0xf, true));
+  } else if (dist == 2) {
+#pragma unroll
+    for (int i = 0; i < N; ++i) dst[i] = __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(src[i]), 0x4E, 0xf, 0xf, true));
+  } else {
+#pragma unroll
+    for (int i = 0; i < N; ++i) dst[i] = __shfl_xor(src[i], dist);
+  }
+}
+
+// PMF kind for constraints of 9 to 32 literals whose spectrum is constant past
+// a window of at most KMAX/2 counts at one end (thresholds near the middle such
+// as at-least-ceil(k/2), exactly-one, at-most-one, exactly-kappa near an end).
+// The pair's G lanes hold J literals each.  Lane l runs the truncated count
+// recursion of the PMF kind over its own literals, giving q_l(c) = Pr[C_l = c]
+// (exact for c <= J, entries past W dropped).  The count over the other lanes
+// of the group has the distribution E_l, the truncated convolution of their q
+// (G = 2: the partner's q; G = 4: the partner's q convolved with the other
+// pair's convolved total), obtained by lane exchanges.  With
+// D_l(c) = sum_b d_{c+b} E_l(b) (d_c = 0 past the window) the objective is
+// FE = c0 + sum_c q_l(c) D_l(c), equal in every lane of the group, and each
+// local literal's gradient is the adjoint of the local recursion started from
+// lambda = D_l.  Every step adds products of probabilities: no cancellation,
+// and about (J + W) operations per literal against about 14 per node and
+// literal (k/2 nodes) on the DFT path.
+// Class data: node table entry floats 0..15 hold d_0..d_15, float 16 holds h.
+template <int KMAX, int G, class SK>
+__device__ __forceinline__ void pmfg_pair(const ProblemDev& P, int cls, const Fetched<KMAX / G>& fp, int lig, int t,
+                                          int logT, const float* xs, SK& sink, float& fchunk, float gsc, float fsc) {
+  constexpr int J = KMAX / G;
+  constexpr int W = KMAX / 2;                 // widest window of the bucket
+  constexpr int WL = J + 1 < W ? J + 1 : W;   // counts of one lane kept
+  static_assert(G == 2 || G == 4, "lane groups of 2 or 4");
+  const int T = 1 << logT;
+  kptr<ClassRec> classes = kconst(P.classes);
+  kptr<float> dt = reinterpret_cast<kptr<float>>(kconst(P.nodes) + classes[cls].node_off);
+  float d[W];
+#pragma unroll
+  for (int c = 0; c < W; ++c) d[c] = dt[c];
+  const float h = dt[16];
+
+  // local recursion; pre[j] = q before literal j (counts 0..j)
+  float pi[J];
+  float pre[J][WL];
+  float q[WL];
+  q[0] = 1.f;
+#pragma unroll
+  for (int c = 1; c < WL; ++c) q[c] = 0.f;
+#pragma unroll
+  for (int j = 0; j < J; ++j) {
+    const int code = fp.code[j];
+    pi[j] = 0.f;  // an empty slot adds nothing to the count
+    if (code != -1) pi[j] = fmaf(-h, flip(x_at(xs, lit_off(code, logT, t)), lit_sign(code)), 0.5f);
+#pragma unroll
+    for (int c = 0; c < WL; ++c)
+      if (c <= j) pre[j][c] = q[c];
+#pragma unroll
+    for (int c = WL - 1; c >= 1; --c)
+      if (c <= j + 1) q[c] = fmaf(pi[j], q[c - 1] - q[c], q[c]);
+    q[0] = fmaf(-pi[j], q[0], q[0]);
+  }
+
+  // D_l(c) = sum_b d_{c+b} E_l(b)
+  float D[WL];
+  if constexpr (G == 2) {
+    float e[WL];
+    xor_exchange(q, e, T);
+#pragma unroll
+    for (int c = 0; c < WL; ++c) {
+      float acc = 0.f;
+#pragma unroll
+      for (int b = 0; b < WL; ++b)
+        if (c + b < W) acc = fmaf(d[c + b], e[b], acc);
+      D[c] = acc;
+    }
+  } else {
+    float x1[WL];
+    xor_exchange(q, x1, T);  // partner in the same half of the group
+    float y2[W];             // the half's total count, truncated
+#pragma unroll
+    for (int c = 0; c < W; ++c) {
+      float acc = 0.f;
+#pragma unroll
+      for (int a = 0; a < WL; ++a)
+        if (c - a >= 0 && c - a < WL) acc = fmaf(q[a], x1[c - a], acc);
+      y2[c] = acc;
+    }
+    float z[W];
+    xor_exchange(y2, z, 2 * T);  // the other half's total
+    // dz(j) = sum_b d_{j+b} z(b); D(c) = sum_a x1(a) dz(c + a)
+    float dz[W];
+#pragma unroll
+    for (int j = 0; j < W; ++j) {
+      float acc = 0.f;
+#pragma unroll
+      for (int b = 0; b < W; ++b)
+        if (j + b < W) acc = fmaf(d[j + b], z[b], acc);
+      dz[j] = acc;
+    }
+#pragma unroll
+    for (int c = 0; c < WL; ++c) {
+      float acc = 0.f;
+#pragma unroll
+      for (int a = 0; a < WL; ++a)
+        if (c + a < W) acc = fmaf(x1[a], dz[c + a], acc);
+      D[c] = acc;
+    }
+  }
+  float fe = 0.f;
+#pragma unroll
+  for (int c = 0; c < WL; ++c) fe = fmaf(q[c], D[c], fe);
+  if (lig == 0) fchunk = fmaf(fp.w * fsc, fe, fchunk);
+
+  // adjoint: lambda = D after the last local literal; dFE/dy_j = -h dFE/dpi_j
+  const float coef = -h * (fp.w * gsc);
+  float* lam = D;
+#pragma unroll
+  for (int j = J - 1; j >= 0; --j) {
+    float gp = 0.f;
+#pragma unroll
+    for (int c = 0; c < WL; ++c) {
+      if (c <= j) {
+        const float diff = (c + 1 < WL ? lam[c + 1] : 0.f) - lam[c];
+        gp = fmaf(pre[j][c], diff, gp);
+        lam[c] = fmaf(pi[j], diff, lam[c]);
+      }
+    }
+    if (fp.code[j] != -1) sink.add(lit_off(fp.code[j], logT, t), flip(coef * gp, lit_sign(fp.code[j])));
+  }
+}
+
 // Per-lane objective partial sums (exact integers): `own` for restart
 // lane mod T; `even` and `odd` for restarts 2 t2 and 2 t2 + 1 of the paths that
 // give a lane two adjacent restarts (t2 = lane mod T/2).
@@ -772,6 +910,12 @@ __device__ __forceinline__ void run_segment(const ProblemDev& P, const Segment& 
           } else {
             dft_pair<KMAX, G>(P, S.m_max, f.cls, f, lig, t, logT, xs, sink, fchunk, gsc, fsc);
           }
+        } else if constexpr (KIND == KIND_PMF && KMAX > 8) {
+          // a class-uniform chunk reads its window coefficients with scalar loads
+          if (chunk_uni)
+            pmfg_pair<KMAX, G>(P, c0, f, lig, t, logT, xs, sink, fchunk, gsc, fsc);
+          else
+            pmfg_pair<KMAX, G>(P, f.cls, f, lig, t, logT, xs, sink, fchunk, gsc, fsc);
         } else if constexpr (KIND == KIND_PMF) {
           // window width of the segment (uniform): 2, 3 or 4 counts
           const int cls = chunk_uni ? c0 : f.cls;
@@ -842,6 +986,13 @@ __device__ __forceinline__ void run_segment(const ProblemDev& P, const Segment& 
   X(KIND, 6, 7)                          \
   X(KIND, 7, 8)
 
+#define PCLS_PMF_BUCKET_CASES(KIND, X) \
+  PCLS_SHORT_BUCKET_CASES(KIND, X)       \
+  X(KIND, 8, 12)                         \
+  X(KIND, 9, 16)                         \
+  X(KIND, 10, 24)                        \
+  X(KIND, 11, 32)
+
 #define PCLS_CASE(KIND, B, KMAX)                                                                    \
   case (KIND)*kNumBuckets + (B):                                                                    \
     if constexpr ((B) <= MAXB) run_segment<KIND, KMAX, MAXB, AT, ST>(P, S, xs, gs, facc, gsc, fsc, tid, logT, ctr, so); \
@@ -855,7 +1006,7 @@ __device__ __forceinline__ void run_any_segment(const ProblemDev& P, const Segme
     PCLS_BUCKET_CASES(KIND_PROD1, PCLS_CASE)
     PCLS_BUCKET_CASES(KIND_PROD2, PCLS_CASE)
     PCLS_BUCKET_CASES(KIND_DFT, PCLS_CASE)
-    PCLS_SHORT_BUCKET_CASES(KIND_PMF, PCLS_CASE)
+    PCLS_PMF_BUCKET_CASES(KIND_PMF, PCLS_CASE)
     default:
       break;
   }
@@ -1129,8 +1280,12 @@ __device__ __forceinline__ void resident_tile(const ProblemDev& P, const TileArg
 // allocation covers its longest code path, so short-constraint problems run a
 // variant with fewer registers and more waves per SIMD) and by the width of the
 // fixed-point gradient accumulator (64-bit, or 32-bit where LDS is short).
-template <int MAXB, class AT>
-__global__ void __launch_bounds__(1024) tile_kernel(ProblemDev P, TileArgs A) {
+// LB: launch bound.  1024-thread workgroups (16 waves per CU) leave each wave
+// 128 registers; the 512-thread instantiation of the variants for long
+// constraints gets 256, for launches that hold one workgroup per CU anyway
+// (state of more than half the LDS).
+template <int MAXB, class AT, int LB = 1024>
+__global__ void __launch_bounds__(LB) tile_kernel(ProblemDev P, TileArgs A) {
   extern __shared__ __attribute__((aligned(16))) unsigned long long lds_raw[];  // 16 B: vector LDS accesses
   A.r0 = blockIdx.x << A.logT;
   resident_tile<MAXB, AT>(P, A, lds_raw);
@@ -1395,6 +1550,10 @@ int32_t device_limits(DeviceLimits& out) {
                               (const void*)tile_kernel<kMaxbShort, unsigned int>,
                               (const void*)tile_kernel<kMaxbMid, unsigned int>,
                               (const void*)tile_kernel<kMaxbAll, unsigned int>,
+                              (const void*)tile_kernel<kMaxbMid, unsigned long long, 512>,
+                              (const void*)tile_kernel<kMaxbAll, unsigned long long, 512>,
+                              (const void*)tile_kernel<kMaxbMid, unsigned int, 512>,
+                              (const void*)tile_kernel<kMaxbAll, unsigned int, 512>,
                               (const void*)stats_kernel<kMaxbShort>,
                               (const void*)stats_kernel<kMaxbMid>,
                               (const void*)stats_kernel<kMaxbAll>};
@@ -1419,6 +1578,7 @@ struct Launch {
   int block;
   size_t lds;
   bool acc64;
+  bool one_per_cu;  // the tile's LDS leaves room for one workgroup per CU
 };
 
 // Restarts per workgroup: largest power of two whose state fits in LDS, at
@@ -1479,6 +1639,7 @@ int32_t choose_launch(const pcls_problem* p, int R, Launch& L) {
   L.block = block;
   L.lds = lds;
   L.acc64 = acc64;
+  L.one_per_cu = lds > cap / 2;
   return PCLS_OK;
 }
 
@@ -1514,16 +1675,24 @@ int32_t launch_tile(const pcls_problem* p, int R, float* d_x, float lr, int n_st
   A.fixed = opt ? opt->d_fixed : nullptr;
   A.tol = opt ? opt->tol : 0.f;
   A.iters = opt ? opt->d_iters : nullptr;
+  // 256-register instantiations for long-constraint launches of 512 threads that
+  // hold one workgroup per CU anyway
+  const bool wide = L.block == 512 && p->max_bucket > kMaxbShort && L.one_per_cu;
+  void (*kern)(ProblemDev, TileArgs);
   if (L.acc64) {
-    auto kern = p->max_bucket <= kMaxbShort ? tile_kernel<kMaxbShort, unsigned long long>
-                                   : (p->max_bucket <= kMaxbMid ? tile_kernel<kMaxbMid, unsigned long long>
-                                                         : tile_kernel<kMaxbAll, unsigned long long>);
-    hipLaunchKernelGGL(kern, dim3(tiles), dim3(L.block), L.lds, stream, p->dev, A);
+    kern = p->max_bucket <= kMaxbShort ? tile_kernel<kMaxbShort, unsigned long long>
+           : p->max_bucket <= kMaxbMid ? (wide ? tile_kernel<kMaxbMid, unsigned long long, 512>
+                                               : tile_kernel<kMaxbMid, unsigned long long>)
+                                       : (wide ? tile_kernel<kMaxbAll, unsigned long long, 512>
+                                               : tile_kernel<kMaxbAll, unsigned long long>);
   } else {
-    auto kern = p->max_bucket <= kMaxbShort ? tile_kernel<kMaxbShort, unsigned int>
-                                   : (p->max_bucket <= kMaxbMid ? tile_kernel<kMaxbMid, unsigned int> : tile_kernel<kMaxbAll, unsigned int>);
-    hipLaunchKernelGGL(kern, dim3(tiles), dim3(L.block), L.lds, stream, p->dev, A);
+    kern = p->max_bucket <= kMaxbShort ? tile_kernel<kMaxbShort, unsigned int>
+           : p->max_bucket <= kMaxbMid ? (wide ? tile_kernel<kMaxbMid, unsigned int, 512>
+                                               : tile_kernel<kMaxbMid, unsigned int>)
+                                       : (wide ? tile_kernel<kMaxbAll, unsigned int, 512>
+                                               : tile_kernel<kMaxbAll, unsigned int>);
   }
+  hipLaunchKernelGGL(kern, dim3(tiles), dim3(L.block), L.lds, stream, p->dev, A);
   PCLS_HIP(hipGetLastError(), "tile_kernel launch");
   return PCLS_OK;
 }

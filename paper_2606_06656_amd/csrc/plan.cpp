@@ -53,7 +53,7 @@ struct ClassKey {
 // Evaluation kind from the shape of the spectrum.  FE = sum_t sp_t Pr[T = t]
 // where Pr[T = 0] = prod u_i, Pr[T = k] = prod p_i (u = (1+y)/2, p = (1-y)/2)
 // and sum_t (-1)^t Pr[T = t] = prod y_i.
-static int pmf_window(const std::vector<int>& sp, float* d, float* h);
+static int pmf_window(const std::vector<int>& sp, float* d, float* h, int nd);
 
 // LDS bank-aware order of one run of short constraints (one lane per pair).
 // A wave instruction reads slot j of a block of consecutive constraints; with T
@@ -171,7 +171,8 @@ static void classify(const std::vector<int>& sp, bool force_generic, ClassRec& C
       C.c2 = (float)(sp[k] - sp[1]);
       return;
     }
-    if (k <= kPmfMaxK && pmf_window(sp, nullptr, nullptr) <= kPmfWindow) {
+    const int w = pmf_window(sp, nullptr, nullptr, 0);
+    if ((k <= kPmfMaxK && w <= kPmfWindow) || (k > kPmfMaxK && k <= kPmfGroupMaxK && 2 * w <= kBucketKmax[bucket_of(k)])) {
       C.kind = KIND_PMF;
       return;
     }
@@ -182,8 +183,8 @@ static void classify(const std::vector<int>& sp, bool force_generic, ClassRec& C
 // PMF kind: the shorter of the two windows.  Counting true literals,
 // FE = sp_k + sum_{t < w} (sp_t - sp_k) Pr[T = t] with w = 1 + the last t where
 // sp_t != sp_k; counting false ones (F = k - T), FE = sp_0 + sum_{f < w}
-// (sp_{k-f} - sp_0) Pr[F = f].  Returns w; fills d[0..3] (zero past w) and h.
-static int pmf_window(const std::vector<int>& sp, float* d, float* h) {
+// (sp_{k-f} - sp_0) Pr[F = f].  Returns w; fills d[0..nd-1] (zero past w) and h.
+static int pmf_window(const std::vector<int>& sp, float* d, float* h, int nd = kPmfWindow) {
   const int k = (int)sp.size() - 1;
   int wt = 0, wf = 0;
   for (int t = 0; t <= k; ++t)
@@ -193,7 +194,7 @@ static int pmf_window(const std::vector<int>& sp, float* d, float* h) {
   const bool count_true = wt <= wf;
   const int w = count_true ? wt : wf;
   if (d) {
-    for (int c = 0; c < kPmfWindow; ++c)
+    for (int c = 0; c < nd; ++c)
       d[c] = (c < w && c <= k) ? (float)(count_true ? sp[c] - sp[k] : sp[k - c] - sp[0]) : 0.f;
     *h = count_true ? 0.5f : -0.5f;
   }
@@ -325,10 +326,10 @@ int32_t build_plan(int32_t n, int32_t m, const int32_t* row_ptr, const int32_t* 
       C.k = k;
       classify(sp, force_generic, C);
       if (C.kind == KIND_DFT) dft_weights(sp, C, P->nodes);
-      if (C.kind == KIND_PMF) {
+      if (C.kind == KIND_PMF && k <= kPmfMaxK) {
         NodeRec N{};
         float d[kPmfWindow], h;
-        C.nyquist = pmf_window(sp, d, &h);  // PMF: the window w (counts kept)
+        C.nyquist = pmf_window(sp, d, &h, kPmfWindow);  // PMF: the window w (counts kept)
         N.ar = d[0];
         N.ai = d[1];
         N.br = d[2];
@@ -338,6 +339,20 @@ int32_t build_plan(int32_t n, int32_t m, const int32_t* row_ptr, const int32_t* 
         C.node_off = (int32_t)P->nodes.size();
         C.n_nodes = 1;
         P->nodes.push_back(N);
+      } else if (C.kind == KIND_PMF) {
+        // lane-group PMF: d_0..d_15 then h, in three node records
+        float rec[24] = {};
+        float h;
+        C.nyquist = pmf_window(sp, rec, &h, 16);
+        rec[16] = h;
+        C.c0 = (float)(h > 0.f ? sp[k] : sp[0]);
+        C.node_off = (int32_t)P->nodes.size();
+        C.n_nodes = 3;
+        for (int r = 0; r < 3; ++r) {
+          NodeRec N;
+          std::memcpy(&N, rec + 8 * r, sizeof N);
+          P->nodes.push_back(N);
+        }
       }
       C.sp_off = (int32_t)P->sp.size();
       for (int t = 0; t <= k; ++t) P->sp.push_back((int8_t)sp[t]);
@@ -491,7 +506,7 @@ int32_t build_plan(int32_t n, int32_t m, const int32_t* row_ptr, const int32_t* 
     auto cost = [](const Segment& s) {
       const int k = kBucketKmax[s.bucket];
       return s.kind == KIND_DFT ? 4 * k * (s.m_max + 1)
-             : s.kind == KIND_PMF ? 6 * k
+             : s.kind == KIND_PMF ? (k <= kPmfMaxK ? 6 * k : k * (k / 2 + 2))
              : (s.kind == KIND_PROD2 ? 2 * k : k);
     };
     return cost(a) > cost(b);

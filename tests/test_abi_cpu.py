@@ -137,8 +137,9 @@ def test_plan_segments_by_kind():
 def _expected_kind(sp):
     """Evaluation path the planner should pick for a spectrum (sp_t = -1 when the
     constraint holds with t true literals): a product form when one exists, the
-    count window when k <= 8 and the spectrum is constant past 4 counts at one
-    end, else the DFT."""
+    count window when the spectrum is constant past w counts at one end with
+    w <= 4 for k <= 8, or w <= half the length bucket (12, 16, 24, 32) for
+    8 < k <= 32, else the DFT."""
     k = len(sp) - 1
     if all(v == sp[0] for v in sp):
         return "const"
@@ -152,10 +153,13 @@ def _expected_kind(sp):
     wf = max([f + 1 for f in range(k + 1) if sp[k - f] != sp[0]], default=0)
     if k <= 8 and min(wt, wf) <= 4:
         return "pmf"
+    bucket = next(b for b in (12, 16, 24, 32, 10 ** 9) if k <= b)
+    if 8 < k <= 32 and 2 * min(wt, wf) <= bucket:
+        return "pmf"
     return "dft"
 
 
-@pytest.mark.parametrize("k", range(1, 13))
+@pytest.mark.parametrize("k", list(range(1, 18)) + [23, 24, 25, 31, 32, 33])
 def test_plan_picks_evaluation_path(k):
     from oracle import coeffs as C
     for ctype in (C.OR, C.XOR, C.CARD_GE, C.NAE, C.EO, C.AMO, C.EK):
