@@ -308,6 +308,20 @@ int32_t pcls_destroy(pcls_problem* p);
 int32_t pcls_constraint_grad_stats(const pcls_problem* p, int32_t R, const float* d_x, uint64_t* d_acc,
                                    float* d_out, void* stream);
 
+/*
+ * pcls_constraint_grad_stats without the caller's accumulator, for callers that
+ * cannot allocate device memory (code under HIP graph capture, serving loops,
+ * harnesses that forbid hipMalloc): the accumulator is a static device array
+ * of the library (2 MiB per device, held until the process ends), and the call
+ * allocates nothing.  Same arguments otherwise, same results bit for bit.
+ * PCLS_E_UNSUPPORTED when n_cons exceeds 262144 (the array's 64-bit words).
+ * Every call on one device shares that device's array and clears it first:
+ * calls that overlap on one device (concurrent streams, threads) race, so
+ * serialise them.
+ */
+int32_t pcls_constraint_grad_stats_noalloc(const pcls_problem* p, int32_t R, const float* d_x, float* d_out,
+                                           void* hip_stream);
+
 /* Thread-local description of the last error; valid until the next call. */
 const char* pcls_last_error(void);
 

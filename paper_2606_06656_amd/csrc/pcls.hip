@@ -1882,6 +1882,62 @@ int32_t batch_attrs() {
   return PCLS_OK;
 }
 
+// Launches of the per-constraint gradient statistic: zero the accumulator
+// (a fill kernel, not a memset node, so the launches can be captured), one
+// workgroup per restart, then the conversion to float in the caller's order.
+int32_t grad_stats_launch(const pcls_problem* p, int32_t R, const float* d_x, unsigned long long* d_acc,
+                          float* d_out, hipStream_t s) {
+  DeviceLimits lim;
+  int32_t st = device_limits(lim);
+  if (st != PCLS_OK) return st;
+  const size_t lds = (size_t)((p->n + 1) & ~1) * 4 + 4 * kMaxSegments;
+  if (lds > (size_t)lim.lds_max)
+    return set_error(PCLS_E_UNSUPPORTED, "state of %d variables does not fit in LDS", p->n);
+  // every term is at most 1, so a constraint's sum over R restarts is at most R k
+  const int bits = (int)std::ceil(std::log2((double)R * (double)std::max(1, p->max_k) + 1.0));
+  const int sc = std::min(40, 60 - bits);
+  hipLaunchKernelGGL(fill_u32_kernel, dim3((2 * p->m + 255) / 256), dim3(256), 0, s, (unsigned int*)d_acc, 0u,
+                     2 * p->m);
+  PCLS_HIP(hipGetLastError(), "fill launch");
+  StatsOut so{d_acc, std::ldexp(1.0f, sc)};
+  const int block = p->n > 4096 ? 1024 : 256;
+  auto kern = p->max_bucket <= kMaxbShort ? stats_kernel<kMaxbShort> : (p->max_bucket <= kMaxbMid ? stats_kernel<kMaxbMid> : stats_kernel<kMaxbAll>);
+  hipLaunchKernelGGL(kern, dim3(R), dim3(block), lds, s, p->dev, d_x, round_up64(R), so);
+  PCLS_HIP(hipGetLastError(), "stats_kernel launch");
+  hipLaunchKernelGGL(stats_finish_kernel, dim3((p->m + 255) / 256), dim3(256), 0, s, d_acc, p->dev.perm, p->m,
+                     std::ldexp(1.0, -sc), d_out);
+  PCLS_HIP(hipGetLastError(), "stats_finish launch");
+  clear_error();
+  return PCLS_OK;
+}
+
+// Static scratch of the allocation-free statistic entry point: one 64-bit
+// accumulator per constraint, at most kStatsScratchWords (2 MiB), held by each
+// device the library runs on until the process ends.  In host code the array's
+// name is not a device address: its address on the current device comes from
+// hipGetSymbolAddress, looked up once per device and kept.  Every call on a
+// device shares that device's array (it is zeroed at the start of each call),
+// so calls that overlap on one device race.
+constexpr int kStatsScratchWords = 1 << 18;
+__device__ __align__(256) unsigned long long scratch[kStatsScratchWords];
+
+std::mutex g_scratch_mu;
+unsigned long long* g_scratch_ptr[64] = {};
+
+int32_t stats_scratch(unsigned long long** out) {
+  int dev = 0;
+  PCLS_HIP(hipGetDevice(&dev), "hipGetDevice");
+  if (dev < 0 || dev >= 64) return set_error(PCLS_E_HIP, "device index %d out of range", dev);
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    PCLS_HIP(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)), "hipGetSymbolAddress(scratch)");
+    g_scratch_ptr[dev] = reinterpret_cast<unsigned long long*>(ptr);
+  }
+  *out = g_scratch_ptr[dev];
+  return PCLS_OK;
+}
+
 }  // namespace
 
 struct pcls_batch {
@@ -2076,29 +2132,23 @@ int32_t pcls_constraint_grad_stats(const pcls_problem* p, int32_t R, const float
   if (R < 1) return set_error(PCLS_E_INVALID, "R must be >= 1");
   if (p->m == 0) return PCLS_OK;
   if (!d_x || !d_acc || !d_out) return set_error(PCLS_E_INVALID, "d_x, d_acc and d_out must not be NULL");
-  DeviceLimits lim;
-  st = device_limits(lim);
+  return grad_stats_launch(p, R, d_x, d_acc, d_out, (hipStream_t)stream);
+}
+
+int32_t pcls_constraint_grad_stats_noalloc(const pcls_problem* p, int32_t R, const float* d_x, float* d_out,
+                                           void* stream) {
+  int32_t st = check_bound(p);
   if (st != PCLS_OK) return st;
-  const size_t lds = (size_t)((p->n + 1) & ~1) * 4 + 4 * kMaxSegments;
-  if (lds > (size_t)lim.lds_max)
-    return set_error(PCLS_E_UNSUPPORTED, "state of %d variables does not fit in LDS", p->n);
-  // every term is at most 1, so a constraint's sum over R restarts is at most R k
-  const int bits = (int)std::ceil(std::log2((double)R * (double)std::max(1, p->max_k) + 1.0));
-  const int sc = std::min(40, 60 - bits);
-  hipStream_t s = (hipStream_t)stream;
-  hipLaunchKernelGGL(fill_u32_kernel, dim3((2 * p->m + 255) / 256), dim3(256), 0, s, (unsigned int*)d_acc, 0u,
-                     2 * p->m);
-  PCLS_HIP(hipGetLastError(), "fill launch");
-  StatsOut so{d_acc, std::ldexp(1.0f, sc)};
-  const int block = p->n > 4096 ? 1024 : 256;
-  auto kern = p->max_bucket <= kMaxbShort ? stats_kernel<kMaxbShort> : (p->max_bucket <= kMaxbMid ? stats_kernel<kMaxbMid> : stats_kernel<kMaxbAll>);
-  hipLaunchKernelGGL(kern, dim3(R), dim3(block), lds, s, p->dev, d_x, round_up64(R), so);
-  PCLS_HIP(hipGetLastError(), "stats_kernel launch");
-  hipLaunchKernelGGL(stats_finish_kernel, dim3((p->m + 255) / 256), dim3(256), 0, s, d_acc, p->dev.perm, p->m,
-                     std::ldexp(1.0, -sc), d_out);
-  PCLS_HIP(hipGetLastError(), "stats_finish launch");
-  clear_error();
-  return PCLS_OK;
+  if (R < 1) return set_error(PCLS_E_INVALID, "R must be >= 1");
+  if (p->m == 0) return PCLS_OK;
+  if (!d_x || !d_out) return set_error(PCLS_E_INVALID, "d_x and d_out must not be NULL");
+  if (p->m > kStatsScratchWords)
+    return set_error(PCLS_E_UNSUPPORTED, "%d constraints exceed the %d words of the library's static scratch", p->m,
+                     kStatsScratchWords);
+  unsigned long long* acc = nullptr;
+  st = stats_scratch(&acc);
+  if (st != PCLS_OK) return st;
+  return grad_stats_launch(p, R, d_x, acc, d_out, (hipStream_t)stream);
 }
 
 int32_t pcls_launch_info(const pcls_problem* p, int32_t R, int32_t* tile_restarts, int32_t* block_threads,

@@ -27,7 +27,7 @@ EXPORTS = ["pcls_plan", "pcls_plan_ex", "pcls_problem_info", "pcls_upload", "pcl
            "pcls_destroy", "pcls_last_error",
            "pcls_batch_create", "pcls_batch_bind", "pcls_batch_set_config", "pcls_batch_get_config",
            "pcls_batch_step", "pcls_batch_capture", "pcls_batch_replay", "pcls_batch_autotune",
-           "pcls_batch_destroy", "pcls_constraint_grad_stats"]
+           "pcls_batch_destroy", "pcls_constraint_grad_stats", "pcls_constraint_grad_stats_noalloc"]
 
 
 class PclsError(RuntimeError):
@@ -103,6 +103,8 @@ def load_library():
     L.pcls_last_error.argtypes = []
     L.pcls_constraint_grad_stats.restype = i32
     L.pcls_constraint_grad_stats.argtypes = [P, i32, vp, vp, vp, vp]
+    L.pcls_constraint_grad_stats_noalloc.restype = i32
+    L.pcls_constraint_grad_stats_noalloc.argtypes = [P, i32, vp, vp, vp]
     _lib = L
     return L
 
@@ -305,6 +307,14 @@ class Problem(Plan):
         out = torch.zeros(m, dtype=torch.float32, device=self.device)
         check(load_library().pcls_constraint_grad_stats(self.handle, int(R), _tptr(X), _tptr(acc), _tptr(out),
                                                         _stream()))
+        return out
+
+    def constraint_grad_stats_noalloc(self, X, R: int, out):
+        """The same statistic into a caller-provided float32 [m] tensor, through
+        the entry point that allocates nothing (the library's static scratch)."""
+        self._check_state(X, R)
+        check(load_library().pcls_constraint_grad_stats_noalloc(self.handle, int(R), _tptr(X), _tptr(out),
+                                                                _stream()))
         return out
 
     def extract(self, X, R: int, want_assign: bool = True):
