@@ -12,11 +12,8 @@ Definition (hidden width 64, three rounds):
                  h_v' = relu(W2 h_v + bv + (1/deg_v) sum_{(c,i): v_i = v} U_{s_i} h_c')
     with W_{+} = Wpn[:64], W_{-} = Wpn[64:], U likewise from Upn;
     x_hat = tanh(wo . h_v + bo).
-Optionally the products follow the mixed-precision scheme of the GPU kernels:
-forward operands rounded to bf16 (round to nearest even); in the backward pass
-the input gradient multiplies the bf16-rounded output gradient by the bf16
-weights, and the weight gradient is taken at full precision from the unrounded
-activations. All other arithmetic stays in FP64.
+Every product is FP64 with the parameters exactly as given: a network whose
+weight matrices are held in bf16 is evaluated by passing the bf16 values.
 """
 from __future__ import annotations
 
@@ -24,30 +21,6 @@ import numpy as np
 import torch
 
 HID, FEAT, LAYERS = 64, 32, 3
-
-
-def bf16(x: torch.Tensor) -> torch.Tensor:
-    return x.to(torch.bfloat16).to(torch.float64)
-
-
-class _Bf16Linear(torch.autograd.Function):
-    """y = bf16(x) bf16(W)^T with the backward pass described in the header."""
-
-    @staticmethod
-    def forward(ctx, x, W):
-        ctx.save_for_backward(x, W)
-        return bf16(x) @ bf16(W).T
-
-    @staticmethod
-    def backward(ctx, dy):
-        x, W = ctx.saved_tensors
-        return bf16(dy) @ bf16(W), dy.T @ x
-
-
-def _linear(emulate_bf16):
-    if emulate_bf16:
-        return _Bf16Linear.apply
-    return lambda x, W: x @ W.T
 
 
 def spec():
@@ -88,9 +61,12 @@ def features(n, row_ptr, lit, ctype, param):
     return torch.tensor(fv), torch.tensor(fc)
 
 
-def forward(instances, params, emulate_bf16=False):
+def forward(instances, params):
     """x_hat for the disjoint union of instances (each: n, row_ptr, lit, ctype, param)."""
-    lin = _linear(emulate_bf16)
+
+    def lin(x, W):
+        return x @ W.T
+
     fvs, fcs, cons, vars_, signs = [], [], [], [], []
     voff = coff = 0
     for (n, row_ptr, lit, ctype, param) in instances:
@@ -126,10 +102,10 @@ def forward(instances, params, emulate_bf16=False):
     return torch.tanh(hv @ params["wo"] + params["bo"])
 
 
-def mse_and_grads(instances, flat, labels, emulate_bf16=False):
+def mse_and_grads(instances, flat, labels):
     """Loss mean (x_hat - y)^2 and the gradient of every parameter (flat, spec order)."""
     params = unflatten(flat)
-    xhat = forward(instances, params, emulate_bf16)
+    xhat = forward(instances, params)
     y = torch.tensor(np.concatenate(labels), dtype=torch.float64)
     loss = ((xhat - y) ** 2).mean()
     loss.backward()

@@ -1,9 +1,12 @@
 // Message-passing network on the variable-constraint graph: gfx950 kernels for
 // the forward pass, the backward pass and the optimiser of the learned restart
 // initialiser.  Dense products use bf16 MFMA (v_mfma_f32_16x16x32_bf16) with
-// float32 accumulation: weights are stored in bf16, activations in float32 and
-// rounded to bf16 (nearest-even) as MFMA operands.  Sparse message passing is a
-// CSR gather (one wave per row, one lane per hidden unit).
+// float32 accumulation: weight matrices are stored in bf16; float32
+// activations (and output gradients) enter as two bf16 operands, the value
+// rounded to bf16 and the rounded remainder, whose sum holds 16 significant
+// bits, so a product with a bf16 weight is exact to about 2^-16 relative.
+// Sparse message passing is a CSR gather (one wave per row, one lane per
+// hidden unit).
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -46,7 +49,8 @@ union Pack8 {
 };
 
 // ------------------------------------------------------------------ GEMM
-// Y[N x M] = beta * Y + A[N x K] op(W) + bias, optionally ReLU'd into Yr.
+// Y[N x M] = beta * Y + A[N x K] op(W) + bias, optionally ReLU'd into Yr;
+// A = A_hi + A_lo in bf16 (two MFMA products per k step), W in bf16.
 // op(W) = W^T for W stored [M][K] (trans_w = 0), W for W stored [K][M] (1).
 // K a multiple of 32 up to 128; M a multiple of 16 up to 128; A row stride lda.
 // Block: 4 waves, 64 rows; op(W) is staged in LDS as Bt[col][k].
@@ -76,18 +80,23 @@ __global__ void __launch_bounds__(256) gemm_kernel(const float* __restrict__ A, 
   for (int j0 = 0; j0 < M; j0 += 16) {
     floatx4 acc = {0.f, 0.f, 0.f, 0.f};
     for (int k0 = 0; k0 < K; k0 += 32) {
-      Pack8 a, b;
+      Pack8 a, al, b;
       if (r < N) {
         const float* ap = A + (size_t)r * lda + k0 + kq;
 #pragma unroll
-        for (int e = 0; e < 8; ++e) a.u[e] = f2bf(ap[e]);
+        for (int e = 0; e < 8; ++e) {
+          const float v = ap[e];
+          a.u[e] = f2bf(v);
+          al.u[e] = f2bf(v - bf2f(a.u[e]));
+        }
       } else {
 #pragma unroll
-        for (int e = 0; e < 8; ++e) a.u[e] = 0;
+        for (int e = 0; e < 8; ++e) a.u[e] = al.u[e] = 0;
       }
 #pragma unroll
       for (int e = 0; e < 8; ++e) b.u[e] = Bt[j0 + (lane & 15)][k0 + kq + e];
       acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a.v, b.v, acc, 0, 0, 0);
+      acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al.v, b.v, acc, 0, 0, 0);
     }
     // lane holds C[4 * (lane / 16) + e][lane % 16]
     const int col = j0 + (lane & 15);

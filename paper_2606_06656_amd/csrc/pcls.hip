@@ -552,29 +552,73 @@ __device__ __forceinline__ void xor_exchange(const float (&src)[N], float (&dst)
   }
 }
 
+// Truncated count recursion over N literals with event probabilities pi:
+// q(c) = Pr[count = c] for c < M, and pre[j] = q before literal j (counts
+// 0..j; entries past j are zero and not kept).
+template <int N, int M>
+__device__ __forceinline__ void count_forward(const float* pi, float (&pre)[N][M], float (&q)[M]) {
+  q[0] = 1.f;
+#pragma unroll
+  for (int c = 1; c < M; ++c) q[c] = 0.f;
+#pragma unroll
+  for (int j = 0; j < N; ++j) {
+#pragma unroll
+    for (int c = 0; c < M; ++c)
+      if (c <= j) pre[j][c] = q[c];
+#pragma unroll
+    for (int c = M - 1; c >= 1; --c)
+      if (c <= j + 1) q[c] = fmaf(pi[j], q[c - 1] - q[c], q[c]);
+    q[0] = fmaf(-pi[j], q[0], q[0]);
+  }
+}
+
+// Reverse mode of count_forward for an objective sum_c q(c) lam(c) (lam past
+// M - 1 is zero): gp[j] = d objective / d pi_j.  lam is consumed.
+template <int N, int M>
+__device__ __forceinline__ void count_adjoint(const float* pi, const float (&pre)[N][M], float (&lam)[M],
+                                              float* gp) {
+#pragma unroll
+  for (int j = N - 1; j >= 0; --j) {
+    float g = 0.f;
+#pragma unroll
+    for (int c = 0; c < M; ++c) {
+      if (c <= j) {
+        const float diff = (c + 1 < M ? lam[c + 1] : 0.f) - lam[c];
+        g = fmaf(pre[j][c], diff, g);
+        lam[c] = fmaf(pi[j], diff, lam[c]);
+      }
+    }
+    gp[j] = g;
+  }
+}
+
 // PMF kind for constraints of 9 to 32 literals whose spectrum is constant past
 // a window of at most KMAX/2 counts at one end (thresholds near the middle such
 // as at-least-ceil(k/2), exactly-one, at-most-one, exactly-kappa near an end).
-// The pair's G lanes hold J literals each.  Lane l runs the truncated count
-// recursion of the PMF kind over its own literals, giving q_l(c) = Pr[C_l = c]
-// (exact for c <= J, entries past W dropped).  The count over the other lanes
-// of the group has the distribution E_l, the truncated convolution of their q
-// (G = 2: the partner's q; G = 4: the partner's q convolved with the other
-// pair's convolved total), obtained by lane exchanges.  With
-// D_l(c) = sum_b d_{c+b} E_l(b) (d_c = 0 past the window) the objective is
-// FE = c0 + sum_c q_l(c) D_l(c), equal in every lane of the group, and each
-// local literal's gradient is the adjoint of the local recursion started from
-// lambda = D_l.  Every step adds products of probabilities: no cancellation,
-// and about (J + W) operations per literal against about 14 per node and
-// literal (k/2 nodes) on the DFT path.
+// The pair's G lanes hold J literals each, in two halves of J/2.  Each half
+// runs the truncated count recursion of the PMF kind, giving its count
+// distribution qa, qb; the lane's own count has q = qa * qb (convolution).  The
+// count over the other lanes of the group has the distribution E, the
+// truncated convolution of their q (G = 2: the partner's q; G = 4: the
+// partner's q convolved with the other pair's convolved total), obtained by
+// lane exchanges.  With D(c) = sum_b d_{c+b} E(b) (d zero past the window),
+// FE = c0 + sum_c q(c) D(c) in every lane of the group; as a function of half
+// a's distribution, FE = c0 + sum_a qa(a) DA(a) with DA(a) = sum_b qb(b) D(a+b),
+// so each literal's gradient is the adjoint of its half's recursion started
+// from DA (or DB).  Every step adds products of probabilities: no
+// cancellation, and about (J + W) operations per literal against about 14 per
+// node and literal (k/2 nodes) on the DFT path.
 // Class data: node table entry floats 0..15 hold d_0..d_15, float 16 holds h.
 template <int KMAX, int G, class SK>
 __device__ __forceinline__ void pmfg_pair(const ProblemDev& P, int cls, const Fetched<KMAX / G>& fp, int lig, int t,
                                           int logT, const float* xs, SK& sink, float& fchunk, float gsc, float fsc) {
   constexpr int J = KMAX / G;
+  constexpr int H = J / 2;                    // literals per half
+  constexpr int MH = H + 1;                   // counts of a half (never truncated: H + 1 <= W)
   constexpr int W = KMAX / 2;                 // widest window of the bucket
   constexpr int WL = J + 1 < W ? J + 1 : W;   // counts of one lane kept
   static_assert(G == 2 || G == 4, "lane groups of 2 or 4");
+  static_assert(J % 2 == 0 && MH <= W, "halves");
   const int T = 1 << logT;
   kptr<ClassRec> classes = kconst(P.classes);
   kptr<float> dt = reinterpret_cast<kptr<float>>(kconst(P.nodes) + classes[cls].node_off);
@@ -583,28 +627,27 @@ __device__ __forceinline__ void pmfg_pair(const ProblemDev& P, int cls, const Fe
   for (int c = 0; c < W; ++c) d[c] = dt[c];
   const float h = dt[16];
 
-  // local recursion; pre[j] = q before literal j (counts 0..j)
   float pi[J];
-  float pre[J][WL];
-  float q[WL];
-  q[0] = 1.f;
-#pragma unroll
-  for (int c = 1; c < WL; ++c) q[c] = 0.f;
 #pragma unroll
   for (int j = 0; j < J; ++j) {
     const int code = fp.code[j];
     pi[j] = 0.f;  // an empty slot adds nothing to the count
     if (code != -1) pi[j] = fmaf(-h, flip(x_at(xs, lit_off(code, logT, t)), lit_sign(code)), 0.5f);
+  }
+  float prea[H][MH], preb[H][MH], qa[MH], qb[MH];
+  count_forward<H, MH>(pi, prea, qa);
+  count_forward<H, MH>(pi + H, preb, qb);
+  float q[WL];
 #pragma unroll
-    for (int c = 0; c < WL; ++c)
-      if (c <= j) pre[j][c] = q[c];
+  for (int c = 0; c < WL; ++c) {
+    float acc = 0.f;
 #pragma unroll
-    for (int c = WL - 1; c >= 1; --c)
-      if (c <= j + 1) q[c] = fmaf(pi[j], q[c - 1] - q[c], q[c]);
-    q[0] = fmaf(-pi[j], q[0], q[0]);
+    for (int a = 0; a < MH; ++a)
+      if (c - a >= 0 && c - a < MH) acc = fmaf(qa[a], qb[c - a], acc);
+    q[c] = acc;
   }
 
-  // D_l(c) = sum_b d_{c+b} E_l(b)
+  // D(c) = sum_b d_{c+b} E(b)
   float D[WL];
   if constexpr (G == 2) {
     float e[WL];
@@ -620,7 +663,7 @@ __device__ __forceinline__ void pmfg_pair(const ProblemDev& P, int cls, const Fe
   } else {
     float x1[WL];
     xor_exchange(q, x1, T);  // partner in the same half of the group
-    float y2[W];             // the half's total count, truncated
+    float y2[W];             // that half's total count, truncated
 #pragma unroll
     for (int c = 0; c < W; ++c) {
       float acc = 0.f;
@@ -650,27 +693,33 @@ __device__ __forceinline__ void pmfg_pair(const ProblemDev& P, int cls, const Fe
       D[c] = acc;
     }
   }
+  // per half: DA(a) = sum_b qb(b) D(a+b), DB(b) = sum_a qa(a) D(a+b)
+  float DA[MH], DB[MH];
+#pragma unroll
+  for (int a = 0; a < MH; ++a) {
+    float sa = 0.f, sb = 0.f;
+#pragma unroll
+    for (int b = 0; b < MH; ++b)
+      if (a + b < WL) {
+        sa = fmaf(qb[b], D[a + b], sa);
+        sb = fmaf(qa[b], D[a + b], sb);
+      }
+    DA[a] = sa;
+    DB[a] = sb;
+  }
   float fe = 0.f;
 #pragma unroll
-  for (int c = 0; c < WL; ++c) fe = fmaf(q[c], D[c], fe);
+  for (int a = 0; a < MH; ++a) fe = fmaf(qa[a], DA[a], fe);
   if (lig == 0) fchunk = fmaf(fp.w * fsc, fe, fchunk);
 
-  // adjoint: lambda = D after the last local literal; dFE/dy_j = -h dFE/dpi_j
+  // dFE/dy_j = -h dFE/dpi_j
+  float gp[J];
+  count_adjoint<H, MH>(pi, prea, DA, gp);
+  count_adjoint<H, MH>(pi + H, preb, DB, gp + H);
   const float coef = -h * (fp.w * gsc);
-  float* lam = D;
 #pragma unroll
-  for (int j = J - 1; j >= 0; --j) {
-    float gp = 0.f;
-#pragma unroll
-    for (int c = 0; c < WL; ++c) {
-      if (c <= j) {
-        const float diff = (c + 1 < WL ? lam[c + 1] : 0.f) - lam[c];
-        gp = fmaf(pre[j][c], diff, gp);
-        lam[c] = fmaf(pi[j], diff, lam[c]);
-      }
-    }
-    if (fp.code[j] != -1) sink.add(lit_off(fp.code[j], logT, t), flip(coef * gp, lit_sign(fp.code[j])));
-  }
+  for (int j = J - 1; j >= 0; --j)
+    if (fp.code[j] != -1) sink.add(lit_off(fp.code[j], logT, t), flip(coef * gp[j], lit_sign(fp.code[j])));
 }
 
 // Per-lane objective partial sums (exact integers): `own` for restart
@@ -903,19 +952,22 @@ __device__ __forceinline__ void run_segment(const ProblemDev& P, const Segment& 
       const int c0 = __builtin_amdgcn_readfirstlane(fp.cls);  // lane 0 holds a valid pair
       const bool chunk_uni = uni || !__any(valid && fp.cls != c0);
       auto eval_pair = [&](auto& sink, const Fetched<J>& f) {
-        if constexpr (KIND == KIND_DFT) {
-          if (chunk_uni) {
-            kptr<ClassRec> cr = kconst(P.classes);
-            dft_pair<KMAX, G>(P, cr[c0].n_nodes, c0, f, lig, t, logT, xs, sink, fchunk, gsc, fsc);
-          } else {
-            dft_pair<KMAX, G>(P, S.m_max, f.cls, f, lig, t, logT, xs, sink, fchunk, gsc, fsc);
+        if constexpr (KIND == KIND_DFT || (KIND == KIND_PMF && KMAX > 8)) {
+          // lanes take turns by class (the first remaining lane's class each
+          // round; one round for a class-uniform chunk), so the class record,
+          // node table and window coefficients are always read with scalar loads
+          for (;;) {
+            const int cc = __builtin_amdgcn_readfirstlane(f.cls);
+            if (f.cls == cc) {
+              if constexpr (KIND == KIND_DFT) {
+                kptr<ClassRec> cr = kconst(P.classes);
+                dft_pair<KMAX, G>(P, cr[cc].n_nodes, cc, f, lig, t, logT, xs, sink, fchunk, gsc, fsc);
+              } else {
+                pmfg_pair<KMAX, G>(P, cc, f, lig, t, logT, xs, sink, fchunk, gsc, fsc);
+              }
+              break;
+            }
           }
-        } else if constexpr (KIND == KIND_PMF && KMAX > 8) {
-          // a class-uniform chunk reads its window coefficients with scalar loads
-          if (chunk_uni)
-            pmfg_pair<KMAX, G>(P, c0, f, lig, t, logT, xs, sink, fchunk, gsc, fsc);
-          else
-            pmfg_pair<KMAX, G>(P, f.cls, f, lig, t, logT, xs, sink, fchunk, gsc, fsc);
         } else if constexpr (KIND == KIND_PMF) {
           // window width of the segment (uniform): 2, 3 or 4 counts
           const int cls = chunk_uni ? c0 : f.cls;
@@ -1280,12 +1332,8 @@ __device__ __forceinline__ void resident_tile(const ProblemDev& P, const TileArg
 // allocation covers its longest code path, so short-constraint problems run a
 // variant with fewer registers and more waves per SIMD) and by the width of the
 // fixed-point gradient accumulator (64-bit, or 32-bit where LDS is short).
-// LB: launch bound.  1024-thread workgroups (16 waves per CU) leave each wave
-// 128 registers; the 512-thread instantiation of the variants for long
-// constraints gets 256, for launches that hold one workgroup per CU anyway
-// (state of more than half the LDS).
-template <int MAXB, class AT, int LB = 1024>
-__global__ void __launch_bounds__(LB) tile_kernel(ProblemDev P, TileArgs A) {
+template <int MAXB, class AT>
+__global__ void __launch_bounds__(1024) tile_kernel(ProblemDev P, TileArgs A) {
   extern __shared__ __attribute__((aligned(16))) unsigned long long lds_raw[];  // 16 B: vector LDS accesses
   A.r0 = blockIdx.x << A.logT;
   resident_tile<MAXB, AT>(P, A, lds_raw);
@@ -1550,10 +1598,6 @@ int32_t device_limits(DeviceLimits& out) {
                               (const void*)tile_kernel<kMaxbShort, unsigned int>,
                               (const void*)tile_kernel<kMaxbMid, unsigned int>,
                               (const void*)tile_kernel<kMaxbAll, unsigned int>,
-                              (const void*)tile_kernel<kMaxbMid, unsigned long long, 512>,
-                              (const void*)tile_kernel<kMaxbAll, unsigned long long, 512>,
-                              (const void*)tile_kernel<kMaxbMid, unsigned int, 512>,
-                              (const void*)tile_kernel<kMaxbAll, unsigned int, 512>,
                               (const void*)stats_kernel<kMaxbShort>,
                               (const void*)stats_kernel<kMaxbMid>,
                               (const void*)stats_kernel<kMaxbAll>};
@@ -1578,7 +1622,6 @@ struct Launch {
   int block;
   size_t lds;
   bool acc64;
-  bool one_per_cu;  // the tile's LDS leaves room for one workgroup per CU
 };
 
 // Restarts per workgroup: largest power of two whose state fits in LDS, at
@@ -1639,7 +1682,6 @@ int32_t choose_launch(const pcls_problem* p, int R, Launch& L) {
   L.block = block;
   L.lds = lds;
   L.acc64 = acc64;
-  L.one_per_cu = lds > cap / 2;
   return PCLS_OK;
 }
 
@@ -1675,22 +1717,15 @@ int32_t launch_tile(const pcls_problem* p, int R, float* d_x, float lr, int n_st
   A.fixed = opt ? opt->d_fixed : nullptr;
   A.tol = opt ? opt->tol : 0.f;
   A.iters = opt ? opt->d_iters : nullptr;
-  // 256-register instantiations for long-constraint launches of 512 threads that
-  // hold one workgroup per CU anyway
-  const bool wide = L.block == 512 && p->max_bucket > kMaxbShort && L.one_per_cu;
   void (*kern)(ProblemDev, TileArgs);
   if (L.acc64) {
     kern = p->max_bucket <= kMaxbShort ? tile_kernel<kMaxbShort, unsigned long long>
-           : p->max_bucket <= kMaxbMid ? (wide ? tile_kernel<kMaxbMid, unsigned long long, 512>
-                                               : tile_kernel<kMaxbMid, unsigned long long>)
-                                       : (wide ? tile_kernel<kMaxbAll, unsigned long long, 512>
-                                               : tile_kernel<kMaxbAll, unsigned long long>);
+           : p->max_bucket <= kMaxbMid ? tile_kernel<kMaxbMid, unsigned long long>
+                                       : tile_kernel<kMaxbAll, unsigned long long>;
   } else {
     kern = p->max_bucket <= kMaxbShort ? tile_kernel<kMaxbShort, unsigned int>
-           : p->max_bucket <= kMaxbMid ? (wide ? tile_kernel<kMaxbMid, unsigned int, 512>
-                                               : tile_kernel<kMaxbMid, unsigned int>)
-                                       : (wide ? tile_kernel<kMaxbAll, unsigned int, 512>
-                                               : tile_kernel<kMaxbAll, unsigned int>);
+           : p->max_bucket <= kMaxbMid ? tile_kernel<kMaxbMid, unsigned int>
+                                       : tile_kernel<kMaxbAll, unsigned int>;
   }
   hipLaunchKernelGGL(kern, dim3(tiles), dim3(L.block), L.lds, stream, p->dev, A);
   PCLS_HIP(hipGetLastError(), "tile_kernel launch");

@@ -39,9 +39,17 @@ def test_gemm(N, K, M, trans):
     Yr = torch.zeros_like(Y)
     LRN.gemm(Ad, K + 3, N, K, Wd, M, trans, bias.to(DEV), Y, M + 5, 1, Yr)
     opW = bf(W).T if trans == 0 else bf(W)
+    # A enters as two bf16 parts, hi = bf16(A) and lo = bf16(A - hi); W is bf16
+    a = A[:, :K].double()
+    ah = bf(a)
+    al = bf(a - ah)
     ref = Y0.double().clone()
-    ref[:, :M] += bf(A[:, :K].double()) @ opW + bias.double()
+    ref[:, :M] += ah @ opW + al @ opW + bias.double()
     np.testing.assert_allclose(Y.cpu().double().numpy(), ref.numpy(), rtol=1e-5, atol=1e-4)
+    # within about 2^-16 relative per term of the float32 operand times the bf16 weight
+    exact = Y0.double().clone()
+    exact[:, :M] += a @ opW + bias.double()
+    np.testing.assert_allclose(Y.cpu().double().numpy(), exact.numpy(), rtol=1e-4, atol=1e-3)
     np.testing.assert_allclose(Yr[:, :M].cpu().double().numpy(), np.maximum(ref[:, :M].numpy(), 0), rtol=1e-5,
                                atol=1e-4)
 
@@ -169,49 +177,69 @@ def oracle_tuple(inst):
     return (inst.n, inst.row_ptr, inst.lit, inst.ctype, inst.param)
 
 
+def bf16_matrices(flat):
+    """The network the kernels hold: weight matrices rounded to bf16 (round to
+    nearest even, as the library's copy), biases and the output head in float32."""
+    out = np.array(flat, np.float64)
+    o = 0
+    for name, shape in M.spec():
+        cnt = int(np.prod(shape))
+        if len(shape) == 2:
+            out[o:o + cnt] = torch.tensor(out[o:o + cnt]).to(torch.bfloat16).double().numpy()
+        o += cnt
+    return out
+
+
 def test_network_forward_and_gradients_match_reference():
+    """The GPU network (bf16 weight matrices, float32 activations entering the
+    MFMA as two bf16 parts, float32 accumulation) against the exact FP64
+    network with the same bf16 weights: forward to 1e-4, every parameter
+    tensor's gradient to 1e-3 relative (16-bit operands: about 2^-16 per
+    product, float32 sums of at most 128 terms).  Against the network with the
+    unrounded float32 master weights the gap is the bf16 rounding of the
+    weights themselves, which the configuration prescribes: the exact FP64
+    network with the bf16 weights shows the same gap, tensor by tensor, to
+    within 1e-3."""
     insts = [synth.mixed_small(n=60, seed=5, kmax=7, count=90), synth.random_ksat(50, 200, 3, seed=6)]
     log("case mpnn full")
     P = LRN.Params(DEV, seed=3)
     G = graph_of(insts)
     net = LRN.MPNN(P)
     xhat = net.forward(G, keep=True)
-    # forward at bf16 operands: tight
-    params = M.unflatten(P.master.cpu().double().numpy())
+    tuples = [oracle_tuple(i) for i in insts]
+    master = P.master.cpu().double().numpy()
+    held = bf16_matrices(master)
     with torch.no_grad():
-        xr = M.forward([oracle_tuple(i) for i in insts], params, emulate_bf16=True).numpy()
-    np.testing.assert_allclose(xhat.cpu().double().numpy(), xr, atol=2e-5)
+        xr = M.forward(tuples, M.unflatten(held)).numpy()
+    np.testing.assert_allclose(xhat.cpu().double().numpy(), xr, atol=1e-4)
     y = [np.random.default_rng(7 + k).uniform(-1, 1, i.n) for k, i in enumerate(insts)]
     yt = torch.tensor(np.concatenate(y), dtype=torch.float32, device=DEV)
     dx, part = net.mse_loss_grad(xhat, yt)
     net.backward(dx)
     g = P.grad.cpu().double().numpy()
-    tuples = [oracle_tuple(i) for i in insts]
-    flat = P.master.cpu().double().numpy()
 
-    def per_tensor(g_ref):
+    def per_tensor(g_ref, g_got=g):
         rel = {}
         for name, shape in M.spec():
             o, _ = P.offsets[name]
             cnt = int(np.prod(shape))
-            a, r = g[o:o + cnt], g_ref[o:o + cnt]
+            a, r = g_got[o:o + cnt], g_ref[o:o + cnt]
             rel[name] = float(np.linalg.norm(a - r) / (np.linalg.norm(r) + 1e-12))
         return rel
 
-    # same mixed-precision scheme in FP64: tight, tensor by tensor
-    loss_e, _, g_e = M.mse_and_grads(tuples, flat, y, emulate_bf16=True)
-    assert part.sum().item() == pytest.approx(loss_e, rel=1e-4)
-    rel_e = per_tensor(g_e)
-    log(f"per-tensor relative gradient error vs the bf16-scheme reference: {rel_e}")
-    assert max(rel_e.values()) <= 1e-2, rel_e
-    # exact FP64 network: bf16 operand rounding bounds the gap; the direction agrees
-    loss_ref, _, g_ref = M.mse_and_grads(tuples, flat, y)
-    assert part.sum().item() == pytest.approx(loss_ref, rel=2e-2)
-    cos = g @ g_ref / (np.linalg.norm(g) * np.linalg.norm(g_ref))
-    assert cos > 0.999, cos
-    rel = per_tensor(g_ref)
-    log(f"per-tensor relative gradient error vs the exact network: {rel}")
-    assert max(rel.values()) <= 0.2, rel
+    loss_h, _, g_h = M.mse_and_grads(tuples, held, y)
+    assert part.sum().item() == pytest.approx(loss_h, rel=1e-4)
+    rel_h = per_tensor(g_h)
+    log(f"per-tensor relative gradient error vs the FP64 network with the bf16 weights: {rel_h}")
+    assert max(rel_h.values()) <= 1e-3, rel_h
+    loss_m, _, g_m = M.mse_and_grads(tuples, master, y)
+    assert part.sum().item() == pytest.approx(loss_m, rel=1e-2)
+    rel_m = per_tensor(g_m)
+    rel_w = per_tensor(g_m, g_h)  # the same gap, exact arithmetic: weight rounding alone
+    log(f"per-tensor gap to the float32-master network: GPU {rel_m}; FP64 with bf16 weights {rel_w}")
+    assert all(abs(rel_m[k] - rel_w[k]) <= 1e-3 for k in rel_m), (rel_m, rel_w)
+    cos = g @ g_m / (np.linalg.norm(g) * np.linalg.norm(g_m))
+    assert cos > 0.99, cos
 
 
 def test_training_reduces_loss():
