@@ -67,8 +67,9 @@ struct FixedAcc<unsigned long long> {
   // patterns; a variable receives exactly one term per occurrence per step, so
   // value() removes count * kMagic once (all arithmetic mod 2^64 is exact).
   static constexpr unsigned long long kMagic = 0x4338000000000000ull;
-  static __device__ __forceinline__ void add(unsigned long long* p, float v) {
-    atomicAdd(p, (unsigned long long)__double_as_longlong((double)v + 6755399441055744.0));
+  static __device__ __forceinline__ void add(unsigned long long* p, float v, bool live = true) {
+    const unsigned long long b = (unsigned long long)__double_as_longlong((double)v + 6755399441055744.0);
+    atomicAdd(p, live ? b : 0ull);
   }
   static __device__ __forceinline__ float value(unsigned long long a, float inv, int count) {
     return (float)((double)(long long)(a - (unsigned long long)count * kMagic) * (double)inv);
@@ -82,10 +83,10 @@ struct FixedAcc<unsigned long long> {
 template <>
 struct FixedAcc<unsigned int> {
   // round to nearest (ties up) in one instruction: v_cvt_rpi computes floor(v + 1/2)
-  static __device__ __forceinline__ void add(unsigned int* p, float v) {
+  static __device__ __forceinline__ void add(unsigned int* p, float v, bool live = true) {
     int r;
     asm("v_cvt_rpi_i32_f32 %0, %1" : "=v"(r) : "v"(v));
-    atomicAdd(p, (unsigned int)r);
+    atomicAdd(p, live ? (unsigned int)r : 0u);
   }
   static __device__ __forceinline__ float value(unsigned int a, float inv, int) { return (float)(int)a * inv; }
 };
@@ -289,14 +290,18 @@ __device__ __forceinline__ AT* g_at(AT* gs, unsigned off) {
 // Where a pair's per-literal gradient terms go: the tile's fixed-point LDS
 // accumulator (GradSink), or a per-lane sum of squares (SquareSink, for the
 // per-constraint gradient statistics).
+// A padded slot (live = false) still issues its add, of zero, at a spare
+// address of the lane (see pad_off): no branch around the atomic.
 template <class AT>
 struct GradSink {
   AT* gs;
-  __device__ __forceinline__ void add(unsigned off, float v) { FixedAcc<AT>::add(g_at(gs, off), v); }
+  __device__ __forceinline__ void add(unsigned off, float v, bool live = true) {
+    FixedAcc<AT>::add(g_at(gs, off), v, live);
+  }
 };
 struct SquareSink {
   float acc;
-  __device__ __forceinline__ void add(unsigned, float v) { acc = fmaf(v, v, acc); }
+  __device__ __forceinline__ void add(unsigned, float v, bool live = true) { acc = live ? fmaf(v, v, acc) : acc; }
 };
 __device__ __forceinline__ unsigned lit_sign(int code) { return (unsigned)code & 0x80000000u; }
 __device__ __forceinline__ float flip(float v, unsigned sb) { return __uint_as_float(__float_as_uint(v) ^ sb); }
@@ -323,9 +328,13 @@ __device__ __forceinline__ ProdConsts prod_consts(kptr<ClassRec> classes, int cl
   return {a, b, c1 * fsc, c2 * fsc, c1 * b * gsc, -0.5f * c2 * gsc};
 }
 
+// Padded slots (code -1, buckets above 8 literals) read x at the lane's spare
+// element `pad` and take the factor 1 by a select, so every slot's LDS read is
+// issued unconditionally (no branch per slot, and the reads overlap).
 template <int NN, int KMAX, int G, class SK>
-__device__ __forceinline__ void prod_pair(const Fetched<KMAX / G>& fp, int lig, int t, int logT, const float* xs, SK& sink,
-                                          float& fchunk, float gsc, float fsc, const ProdParams& pp) {
+__device__ __forceinline__ void prod_pair(const Fetched<KMAX / G>& fp, int lig, int t, int logT, unsigned pad,
+                                          const float* xs, SK& sink, float& fchunk, float gsc, float fsc,
+                                          const ProdParams& pp) {
   constexpr int J = KMAX / G;
   constexpr bool kExact = KMAX <= 8;  // buckets up to 8 hold a single length
   const int T = 1 << logT;
@@ -336,15 +345,12 @@ __device__ __forceinline__ void prod_pair(const Fetched<KMAX / G>& fp, int lig, 
 #pragma unroll
   for (int j = 0; j < J; ++j) {
     const int code = fp.code[j];
-    el[j] = 0;
-    f1[j] = 1.f;
+    const bool live = kExact || code != -1;
+    el[j] = live ? lit_off(code, logT, t) : pad;
+    const float y = flip(x_at(xs, el[j]), lit_sign(code));
+    f1[j] = live ? fmaf(b1, y, a1) : 1.f;
     f2[j] = 1.f;
-    if (kExact || code != -1) {
-      el[j] = lit_off(code, logT, t);
-      const float y = flip(x_at(xs, el[j]), lit_sign(code));
-      f1[j] = fmaf(b1, y, a1);
-      if constexpr (NN == 2) f2[j] = fmaf(-0.5f, y, 0.5f);
-    }
+    if constexpr (NN == 2) f2[j] = live ? fmaf(-0.5f, y, 0.5f) : 1.f;
   }
   float pre1[J], pre2[J];
   float run1 = 1.f, run2 = 1.f;
@@ -379,7 +385,7 @@ __device__ __forceinline__ void prod_pair(const Fetched<KMAX / G>& fp, int lig, 
       g = fmaf(s2 * pre2[j], suf2, g);
       suf2 *= f2[j];
     }
-    if (kExact || fp.code[j] != -1) sink.add(el[j], flip(g, lit_sign(fp.code[j])));
+    sink.add(el[j], flip(g, lit_sign(fp.code[j])), kExact || fp.code[j] != -1);
   }
 }
 
@@ -389,8 +395,8 @@ __device__ __forceinline__ void prod_pair(const Fetched<KMAX / G>& fp, int lig, 
 // record and the node table are read with scalar loads.
 template <int KMAX, int G, class SK>
 __device__ __forceinline__ void dft_pair(const ProblemDev& P, int m_max, int cls, const Fetched<KMAX / G>& fp,
-                                         int lig, int t, int logT, const float* xs, SK& sink, float& fchunk,
-                                         float gsc, float fsc) {
+                                         int lig, int t, int logT, unsigned pad, const float* xs, SK& sink,
+                                         float& fchunk, float gsc, float fsc) {
   constexpr int J = KMAX / G;
   constexpr bool kExact = KMAX <= 8;  // buckets up to 8 hold a single length
   const int T = 1 << logT;
@@ -405,13 +411,11 @@ __device__ __forceinline__ void dft_pair(const ProblemDev& P, int m_max, int cls
 #pragma unroll
   for (int j = 0; j < J; ++j) {
     const int code = fp.code[j];
-    el[j] = 0;
-    y[j] = 1.f;
+    const bool live = kExact || code != -1;
+    el[j] = live ? lit_off(code, logT, t) : pad;  // padded slots: y = 1, read issued anyway
+    const float xv = flip(x_at(xs, el[j]), lit_sign(code));
+    y[j] = live ? xv : 1.f;
     g[j] = 0.f;
-    if (kExact || code != -1) {
-      el[j] = lit_off(code, logT, t);
-      y[j] = flip(x_at(xs, el[j]), lit_sign(code));
-    }
   }
   float fe = 0.f;
   if (nyquist) {  // real node omega^(K/2) = -1: factor y, padded slots hold y = 1
@@ -465,10 +469,8 @@ __device__ __forceinline__ void dft_pair(const ProblemDev& P, int m_max, int cls
   if (lig == 0) fchunk = fmaf(fp.w * fsc, fe, fchunk);
 #pragma unroll
   for (int j = 0; j < J; ++j) {
-    if (kExact || fp.code[j] != -1) {
-      const float gv = (fp.w * gsc) * g[j];
-      sink.add(el[j], flip(gv, lit_sign(fp.code[j])));
-    }
+    const float gv = (fp.w * gsc) * g[j];
+    sink.add(el[j], flip(gv, lit_sign(fp.code[j])), kExact || fp.code[j] != -1);
   }
 }
 
@@ -611,7 +613,8 @@ __device__ __forceinline__ void count_adjoint(const float* pi, const float (&pre
 // Class data: node table entry floats 0..15 hold d_0..d_15, float 16 holds h.
 template <int KMAX, int G, class SK>
 __device__ __forceinline__ void pmfg_pair(const ProblemDev& P, int cls, const Fetched<KMAX / G>& fp, int lig, int t,
-                                          int logT, const float* xs, SK& sink, float& fchunk, float gsc, float fsc) {
+                                          int logT, unsigned pad, const float* xs, SK& sink, float& fchunk,
+                                          float gsc, float fsc) {
   constexpr int J = KMAX / G;
   constexpr int H = J / 2;                    // literals per half
   constexpr int MH = H + 1;                   // counts of a half (never truncated: H + 1 <= W)
@@ -631,8 +634,8 @@ __device__ __forceinline__ void pmfg_pair(const ProblemDev& P, int cls, const Fe
 #pragma unroll
   for (int j = 0; j < J; ++j) {
     const int code = fp.code[j];
-    pi[j] = 0.f;  // an empty slot adds nothing to the count
-    if (code != -1) pi[j] = fmaf(-h, flip(x_at(xs, lit_off(code, logT, t)), lit_sign(code)), 0.5f);
+    const float xv = flip(x_at(xs, code != -1 ? lit_off(code, logT, t) : pad), lit_sign(code));
+    pi[j] = code != -1 ? fmaf(-h, xv, 0.5f) : 0.f;  // an empty slot adds nothing to the count
   }
   float prea[H][MH], preb[H][MH], qa[MH], qb[MH];
   count_forward<H, MH>(pi, prea, qa);
@@ -719,7 +722,8 @@ __device__ __forceinline__ void pmfg_pair(const ProblemDev& P, int cls, const Fe
   const float coef = -h * (fp.w * gsc);
 #pragma unroll
   for (int j = J - 1; j >= 0; --j)
-    if (fp.code[j] != -1) sink.add(lit_off(fp.code[j], logT, t), flip(coef * gp[j], lit_sign(fp.code[j])));
+    sink.add(fp.code[j] != -1 ? lit_off(fp.code[j], logT, t) : pad, flip(coef * gp[j], lit_sign(fp.code[j])),
+             fp.code[j] != -1);
 }
 
 // Per-lane objective partial sums (exact integers): `own` for restart
@@ -912,6 +916,9 @@ __device__ __forceinline__ void run_segment(const ProblemDev& P, const Segment& 
   const int lig = (lane >> logT) & (G - 1);
   const int sub = lane >> (logT + LG);
   const int per_wave = kWave >> (logT + LG);  // pairs one wave covers side by side
+  // the lane's spare element for padded slots: a valid (variable, restart) that
+  // differs across lanes, so the zero adds of padded slots do not collide
+  const unsigned pad = lit_off(min(lane, P.n - 1), logT, t);
   kptr<ClassRec> classes = kconst(P.classes);
   const bool uni = S.cls_fixed >= 0;
   ProdParams pp_uni{};
@@ -961,9 +968,9 @@ __device__ __forceinline__ void run_segment(const ProblemDev& P, const Segment& 
             if (f.cls == cc) {
               if constexpr (KIND == KIND_DFT) {
                 kptr<ClassRec> cr = kconst(P.classes);
-                dft_pair<KMAX, G>(P, cr[cc].n_nodes, cc, f, lig, t, logT, xs, sink, fchunk, gsc, fsc);
+                dft_pair<KMAX, G>(P, cr[cc].n_nodes, cc, f, lig, t, logT, pad, xs, sink, fchunk, gsc, fsc);
               } else {
-                pmfg_pair<KMAX, G>(P, cc, f, lig, t, logT, xs, sink, fchunk, gsc, fsc);
+                pmfg_pair<KMAX, G>(P, cc, f, lig, t, logT, pad, xs, sink, fchunk, gsc, fsc);
               }
               break;
             }
@@ -980,7 +987,7 @@ __device__ __forceinline__ void run_segment(const ProblemDev& P, const Segment& 
           }
         } else {
           const ProdParams pp = uni ? pp_uni : prod_params(classes, chunk_uni ? c0 : f.cls);
-          prod_pair<KIND == KIND_PROD2 ? 2 : 1, KMAX, G>(f, lig, t, logT, xs, sink, fchunk, gsc, fsc, pp);
+          prod_pair<KIND == KIND_PROD2 ? 2 : 1, KMAX, G>(f, lig, t, logT, pad, xs, sink, fchunk, gsc, fsc, pp);
         }
       };
       if constexpr (ST) {
