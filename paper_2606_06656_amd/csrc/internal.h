@@ -40,6 +40,14 @@ constexpr int kMaxbMid = 11;                 // k <= 32
 constexpr int kMaxbAll = kNumBuckets - 1;    // k <= 256
 constexpr int kMaxK = 256;
 constexpr int kMaxSegments = 4 * kNumBuckets;  // (kind, bucket) pairs of the non-constant kinds
+// Pad rows: problems with constraints longer than 8 literals get kPadRows extra
+// rows in the on-chip state, held at x = +1 and never stepped.  A slot past a
+// constraint's end (length buckets above 8) codes one of these rows, with the
+// literal sign chosen so that the slot's factor is exactly 1 (its gradient
+// term lands in the pad row, whose accumulator is never read).  Constraint q
+// of a segment uses pad row q mod kPadRows, so the lanes of one instruction
+// hit different rows.
+constexpr int kPadRows = 64;
 
 // Lanes per (constraint, restart) pair: one lane holds up to 16 literals of a
 // product kind or 8 of the DFT and PMF kinds (register budget at 4 waves per SIMD);
@@ -99,6 +107,7 @@ struct NodeRec {
 // Device view of a planned problem (passed by value to kernels).
 struct ProblemDev {
   int32_t n, m, L;
+  int32_t n_pad;                 // pad rows after the n variables (0 or kPadRows)
   int32_t n_segments;
   int32_t n_classes;
   float f_const;                 // sum_c w_c c0_c
@@ -107,7 +116,8 @@ struct ProblemDev {
   const NodeRec* nodes;
   const int8_t* sp;              // spectra
   const int32_t* litT;           // per segment: [KMAX][c_count] literal codes: variable in bits 0..30,
-                                 // bit 31 set for a negated literal, -1 for an empty slot
+                                 // bit 31 set for a negated literal; a slot past the constraint's
+                                 // end codes a pad row (variable >= n)
   const int32_t* c_k;            // per constraint length (planned order)
   const int32_t* c_cls;          // per constraint class
   const float* c_w;              // per constraint weight

@@ -67,9 +67,8 @@ struct FixedAcc<unsigned long long> {
   // patterns; a variable receives exactly one term per occurrence per step, so
   // value() removes count * kMagic once (all arithmetic mod 2^64 is exact).
   static constexpr unsigned long long kMagic = 0x4338000000000000ull;
-  static __device__ __forceinline__ void add(unsigned long long* p, float v, bool live = true) {
-    const unsigned long long b = (unsigned long long)__double_as_longlong((double)v + 6755399441055744.0);
-    atomicAdd(p, live ? b : 0ull);
+  static __device__ __forceinline__ void add(unsigned long long* p, float v) {
+    atomicAdd(p, (unsigned long long)__double_as_longlong((double)v + 6755399441055744.0));
   }
   static __device__ __forceinline__ float value(unsigned long long a, float inv, int count) {
     return (float)((double)(long long)(a - (unsigned long long)count * kMagic) * (double)inv);
@@ -83,10 +82,10 @@ struct FixedAcc<unsigned long long> {
 template <>
 struct FixedAcc<unsigned int> {
   // round to nearest (ties up) in one instruction: v_cvt_rpi computes floor(v + 1/2)
-  static __device__ __forceinline__ void add(unsigned int* p, float v, bool live = true) {
+  static __device__ __forceinline__ void add(unsigned int* p, float v) {
     int r;
     asm("v_cvt_rpi_i32_f32 %0, %1" : "=v"(r) : "v"(v));
-    atomicAdd(p, live ? (unsigned int)r : 0u);
+    atomicAdd(p, (unsigned int)r);
   }
   static __device__ __forceinline__ float value(unsigned int a, float inv, int) { return (float)(int)a * inv; }
 };
@@ -290,18 +289,19 @@ __device__ __forceinline__ AT* g_at(AT* gs, unsigned off) {
 // Where a pair's per-literal gradient terms go: the tile's fixed-point LDS
 // accumulator (GradSink), or a per-lane sum of squares (SquareSink, for the
 // per-constraint gradient statistics).
-// A padded slot (live = false) still issues its add, of zero, at a spare
-// address of the lane (see pad_off): no branch around the atomic.
+// Terms of pad slots (code of a pad row, variable >= n) go to the pad row's
+// accumulator, which is never read; the statistics sink skips them.
 template <class AT>
 struct GradSink {
   AT* gs;
-  __device__ __forceinline__ void add(unsigned off, float v, bool live = true) {
-    FixedAcc<AT>::add(g_at(gs, off), v, live);
-  }
+  __device__ __forceinline__ void add(unsigned off, float v, int) { FixedAcc<AT>::add(g_at(gs, off), v); }
 };
 struct SquareSink {
   float acc;
-  __device__ __forceinline__ void add(unsigned, float v, bool live = true) { acc = live ? fmaf(v, v, acc) : acc; }
+  int n;
+  __device__ __forceinline__ void add(unsigned, float v, int code) {
+    acc = ((code & 0x7fffffff) < n) ? fmaf(v, v, acc) : acc;
+  }
 };
 __device__ __forceinline__ unsigned lit_sign(int code) { return (unsigned)code & 0x80000000u; }
 __device__ __forceinline__ float flip(float v, unsigned sb) { return __uint_as_float(__float_as_uint(v) ^ sb); }
@@ -328,11 +328,11 @@ __device__ __forceinline__ ProdConsts prod_consts(kptr<ClassRec> classes, int cl
   return {a, b, c1 * fsc, c2 * fsc, c1 * b * gsc, -0.5f * c2 * gsc};
 }
 
-// Padded slots (code -1, buckets above 8 literals) read x at the lane's spare
-// element `pad` and take the factor 1 by a select, so every slot's LDS read is
-// issued unconditionally (no branch per slot, and the reads overlap).
+// Slots past a constraint's end code a pad row whose factor is exactly 1 (the
+// sign is chosen by the planner), except the second node of PROD2, which a
+// select sets to 1: every slot is read and processed without a branch.
 template <int NN, int KMAX, int G, class SK>
-__device__ __forceinline__ void prod_pair(const Fetched<KMAX / G>& fp, int lig, int t, int logT, unsigned pad,
+__device__ __forceinline__ void prod_pair(const Fetched<KMAX / G>& fp, int lig, int t, int logT, int n,
                                           const float* xs, SK& sink, float& fchunk, float gsc, float fsc,
                                           const ProdParams& pp) {
   constexpr int J = KMAX / G;
@@ -345,12 +345,11 @@ __device__ __forceinline__ void prod_pair(const Fetched<KMAX / G>& fp, int lig, 
 #pragma unroll
   for (int j = 0; j < J; ++j) {
     const int code = fp.code[j];
-    const bool live = kExact || code != -1;
-    el[j] = live ? lit_off(code, logT, t) : pad;
+    el[j] = lit_off(code, logT, t);
     const float y = flip(x_at(xs, el[j]), lit_sign(code));
-    f1[j] = live ? fmaf(b1, y, a1) : 1.f;
+    f1[j] = fmaf(b1, y, a1);
     f2[j] = 1.f;
-    if constexpr (NN == 2) f2[j] = live ? fmaf(-0.5f, y, 0.5f) : 1.f;
+    if constexpr (NN == 2) f2[j] = (kExact || (code & 0x7fffffff) < n) ? fmaf(-0.5f, y, 0.5f) : 1.f;
   }
   float pre1[J], pre2[J];
   float run1 = 1.f, run2 = 1.f;
@@ -385,7 +384,7 @@ __device__ __forceinline__ void prod_pair(const Fetched<KMAX / G>& fp, int lig, 
       g = fmaf(s2 * pre2[j], suf2, g);
       suf2 *= f2[j];
     }
-    sink.add(el[j], flip(g, lit_sign(fp.code[j])), kExact || fp.code[j] != -1);
+    sink.add(el[j], flip(g, lit_sign(fp.code[j])), fp.code[j]);
   }
 }
 
@@ -395,8 +394,8 @@ __device__ __forceinline__ void prod_pair(const Fetched<KMAX / G>& fp, int lig, 
 // record and the node table are read with scalar loads.
 template <int KMAX, int G, class SK>
 __device__ __forceinline__ void dft_pair(const ProblemDev& P, int m_max, int cls, const Fetched<KMAX / G>& fp,
-                                         int lig, int t, int logT, unsigned pad, const float* xs, SK& sink,
-                                         float& fchunk, float gsc, float fsc) {
+                                         int lig, int t, int logT, const float* xs, SK& sink, float& fchunk,
+                                         float gsc, float fsc) {
   constexpr int J = KMAX / G;
   constexpr bool kExact = KMAX <= 8;  // buckets up to 8 hold a single length
   const int T = 1 << logT;
@@ -411,10 +410,8 @@ __device__ __forceinline__ void dft_pair(const ProblemDev& P, int m_max, int cls
 #pragma unroll
   for (int j = 0; j < J; ++j) {
     const int code = fp.code[j];
-    const bool live = kExact || code != -1;
-    el[j] = live ? lit_off(code, logT, t) : pad;  // padded slots: y = 1, read issued anyway
-    const float xv = flip(x_at(xs, el[j]), lit_sign(code));
-    y[j] = live ? xv : 1.f;
+    el[j] = lit_off(code, logT, t);  // pad slots read y = 1: factor alpha + beta = 1 exactly
+    y[j] = flip(x_at(xs, el[j]), lit_sign(code));
     g[j] = 0.f;
   }
   float fe = 0.f;
@@ -445,8 +442,7 @@ __device__ __forceinline__ void dft_pair(const ProblemDev& P, int m_max, int cls
 #pragma unroll
       for (int j = 0; j < J; ++j) {
         pre[j] = run;
-        const bool ok = kExact || fp.code[j] != -1;
-        const cf f = ok ? cf{fmaf(N.br, y[j], N.ar), fmaf(N.bi, y[j], N.ai)} : cf{1.f, 0.f};
+        const cf f{fmaf(N.br, y[j], N.ar), fmaf(N.bi, y[j], N.ai)};
         run = cmul(run, f);
       }
       const cf xp = grp_prefix_c<G>(run, lig, T);
@@ -460,8 +456,7 @@ __device__ __forceinline__ void dft_pair(const ProblemDev& P, int m_max, int cls
 #pragma unroll
       for (int j = J - 1; j >= 0; --j) {
         g[j] = fmaf(pre[j].r, S.r, fmaf(-pre[j].i, S.i, g[j]));  // Re(pre_j * S_j)
-        const bool ok = kExact || fp.code[j] != -1;
-        const cf f = ok ? cf{fmaf(N.br, y[j], N.ar), fmaf(N.bi, y[j], N.ai)} : cf{1.f, 0.f};
+        const cf f{fmaf(N.br, y[j], N.ar), fmaf(N.bi, y[j], N.ai)};
         S = cmul(S, f);
       }
     }
@@ -470,7 +465,7 @@ __device__ __forceinline__ void dft_pair(const ProblemDev& P, int m_max, int cls
 #pragma unroll
   for (int j = 0; j < J; ++j) {
     const float gv = (fp.w * gsc) * g[j];
-    sink.add(el[j], flip(gv, lit_sign(fp.code[j])), kExact || fp.code[j] != -1);
+    sink.add(el[j], flip(gv, lit_sign(fp.code[j])), fp.code[j]);
   }
 }
 
@@ -533,7 +528,7 @@ __device__ __forceinline__ void pmf_pair(const ProblemDev& P, int cls, const Fet
     }
 #pragma unroll
     for (int c = 0; c < W; ++c) lam[c] = fmaf(pi[j], diff[c], lam[c]);
-    sink.add(el[j], flip(coef * gp, lit_sign(fp.code[j])));
+    sink.add(el[j], flip(coef * gp, lit_sign(fp.code[j])), fp.code[j]);
   }
 }
 
@@ -613,8 +608,7 @@ __device__ __forceinline__ void count_adjoint(const float* pi, const float (&pre
 // Class data: node table entry floats 0..15 hold d_0..d_15, float 16 holds h.
 template <int KMAX, int G, class SK>
 __device__ __forceinline__ void pmfg_pair(const ProblemDev& P, int cls, const Fetched<KMAX / G>& fp, int lig, int t,
-                                          int logT, unsigned pad, const float* xs, SK& sink, float& fchunk,
-                                          float gsc, float fsc) {
+                                          int logT, const float* xs, SK& sink, float& fchunk, float gsc, float fsc) {
   constexpr int J = KMAX / G;
   constexpr int H = J / 2;                    // literals per half
   constexpr int MH = H + 1;                   // counts of a half (never truncated: H + 1 <= W)
@@ -633,9 +627,8 @@ __device__ __forceinline__ void pmfg_pair(const ProblemDev& P, int cls, const Fe
   float pi[J];
 #pragma unroll
   for (int j = 0; j < J; ++j) {
-    const int code = fp.code[j];
-    const float xv = flip(x_at(xs, code != -1 ? lit_off(code, logT, t) : pad), lit_sign(code));
-    pi[j] = code != -1 ? fmaf(-h, xv, 0.5f) : 0.f;  // an empty slot adds nothing to the count
+    const int code = fp.code[j];  // a pad slot reads y = 2h: pi = 0, it adds nothing to the count
+    pi[j] = fmaf(-h, flip(x_at(xs, lit_off(code, logT, t)), lit_sign(code)), 0.5f);
   }
   float prea[H][MH], preb[H][MH], qa[MH], qb[MH];
   count_forward<H, MH>(pi, prea, qa);
@@ -722,8 +715,7 @@ __device__ __forceinline__ void pmfg_pair(const ProblemDev& P, int cls, const Fe
   const float coef = -h * (fp.w * gsc);
 #pragma unroll
   for (int j = J - 1; j >= 0; --j)
-    sink.add(fp.code[j] != -1 ? lit_off(fp.code[j], logT, t) : pad, flip(coef * gp[j], lit_sign(fp.code[j])),
-             fp.code[j] != -1);
+    sink.add(lit_off(fp.code[j], logT, t), flip(coef * gp[j], lit_sign(fp.code[j])), fp.code[j]);
 }
 
 // Per-lane objective partial sums (exact integers): `own` for restart
@@ -916,9 +908,6 @@ __device__ __forceinline__ void run_segment(const ProblemDev& P, const Segment& 
   const int lig = (lane >> logT) & (G - 1);
   const int sub = lane >> (logT + LG);
   const int per_wave = kWave >> (logT + LG);  // pairs one wave covers side by side
-  // the lane's spare element for padded slots: a valid (variable, restart) that
-  // differs across lanes, so the zero adds of padded slots do not collide
-  const unsigned pad = lit_off(min(lane, P.n - 1), logT, t);
   kptr<ClassRec> classes = kconst(P.classes);
   const bool uni = S.cls_fixed >= 0;
   ProdParams pp_uni{};
@@ -968,9 +957,9 @@ __device__ __forceinline__ void run_segment(const ProblemDev& P, const Segment& 
             if (f.cls == cc) {
               if constexpr (KIND == KIND_DFT) {
                 kptr<ClassRec> cr = kconst(P.classes);
-                dft_pair<KMAX, G>(P, cr[cc].n_nodes, cc, f, lig, t, logT, pad, xs, sink, fchunk, gsc, fsc);
+                dft_pair<KMAX, G>(P, cr[cc].n_nodes, cc, f, lig, t, logT, xs, sink, fchunk, gsc, fsc);
               } else {
-                pmfg_pair<KMAX, G>(P, cc, f, lig, t, logT, pad, xs, sink, fchunk, gsc, fsc);
+                pmfg_pair<KMAX, G>(P, cc, f, lig, t, logT, xs, sink, fchunk, gsc, fsc);
               }
               break;
             }
@@ -987,7 +976,7 @@ __device__ __forceinline__ void run_segment(const ProblemDev& P, const Segment& 
           }
         } else {
           const ProdParams pp = uni ? pp_uni : prod_params(classes, chunk_uni ? c0 : f.cls);
-          prod_pair<KIND == KIND_PROD2 ? 2 : 1, KMAX, G>(f, lig, t, logT, pad, xs, sink, fchunk, gsc, fsc, pp);
+          prod_pair<KIND == KIND_PROD2 ? 2 : 1, KMAX, G>(f, lig, t, logT, P.n, xs, sink, fchunk, gsc, fsc, pp);
         }
       };
       if constexpr (ST) {
@@ -996,7 +985,7 @@ __device__ __forceinline__ void run_segment(const ProblemDev& P, const Segment& 
         if (valid) {
           Fetched<J> f1 = fp;
           f1.w = 1.f;
-          SquareSink sk{0.f};
+          SquareSink sk{0.f, P.n};
           eval_pair(sk, f1);
           sq = sk.acc;
         }
@@ -1138,11 +1127,12 @@ template <int MAXB, class AT>
 __device__ __forceinline__ void resident_tile(const ProblemDev& P, const TileArgs& A, unsigned long long* lds_raw) {
   const int logT = A.logT;
   const int T = 1 << logT;
-  const int NT = P.n << logT;
+  const int NT = P.n << logT;                 // state elements stepped
+  const int NR = (P.n + P.n_pad) << logT;     // with the pad rows
   float* xs = reinterpret_cast<float*>(lds_raw);
-  AT* gs = reinterpret_cast<AT*>(reinterpret_cast<char*>(lds_raw) + ((size_t)NT * 4 + 7) / 8 * 8);
+  AT* gs = reinterpret_cast<AT*>(reinterpret_cast<char*>(lds_raw) + ((size_t)NR * 4 + 15) / 16 * 16);
   unsigned long long* Fl =
-      reinterpret_cast<unsigned long long*>(reinterpret_cast<char*>(gs) + ((size_t)NT * sizeof(AT) + 7) / 8 * 8);
+      reinterpret_cast<unsigned long long*>(reinterpret_cast<char*>(gs) + ((size_t)NR * sizeof(AT) + 7) / 8 * 8);
   const int n_fl = logT >= 1 ? 3 * kWave : kWave;  // slots per set; two sets
   int* ctr = reinterpret_cast<int*>(Fl + 2 * n_fl);
   int* conv = ctr + kMaxSegments;
@@ -1158,6 +1148,10 @@ __device__ __forceinline__ void resident_tile(const ProblemDev& P, const TileArg
     float x = A.X[(size_t)v * ldx + r0 + tt];
     if (A.fixed && A.fixed[v] != 0) x = (float)A.fixed[v];
     xs[i] = x;
+    gs[i] = 0;
+  }
+  for (int i = NT + tid; i < NR; i += nth) {  // pad rows: x = +1, never stepped
+    xs[i] = 1.f;
     gs[i] = 0;
   }
   for (int i = tid; i < 2 * n_fl; i += nth) Fl[i] = 0ull;
@@ -1356,9 +1350,9 @@ __global__ void __launch_bounds__(1024) stats_kernel(ProblemDev P, const float* 
                                                      StatsOut so) {
   extern __shared__ __attribute__((aligned(16))) unsigned long long lds_raw[];  // 16 B: vector LDS accesses
   float* xs = reinterpret_cast<float*>(lds_raw);
-  int* ctr = reinterpret_cast<int*>(xs + ((P.n + 1) & ~1));
+  int* ctr = reinterpret_cast<int*>(xs + ((P.n + P.n_pad + 1) & ~1));
   const int r = blockIdx.x;
-  for (int i = threadIdx.x; i < P.n; i += blockDim.x) xs[i] = X[(size_t)i * ldx + r];
+  for (int i = threadIdx.x; i < P.n + P.n_pad; i += blockDim.x) xs[i] = i < P.n ? X[(size_t)i * ldx + r] : 1.f;
   if ((int)threadIdx.x < P.n_segments) ctr[threadIdx.x] = 0;
   __syncthreads();
   ObjAcc facc{0, 0, 0};
@@ -1397,6 +1391,7 @@ struct BatchItem {
 __device__ __forceinline__ ProblemDev load_problem(kptr<BatchInst> bi) {
   ProblemDev P;
   P.n = bi->P.n;
+  P.n_pad = bi->P.n_pad;
   P.m = bi->P.m;
   P.L = bi->P.L;
   P.n_segments = bi->P.n_segments;
@@ -1618,11 +1613,14 @@ int32_t device_limits(DeviceLimits& out) {
 
 // LDS of one workgroup: x[n][T] float, g[n][T] fixed point (4 or 8 bytes),
 // F[T] 64-bit, each region 8-byte aligned.
-size_t tile_lds_bytes(int n, int T, int acc_bytes) {
-  const size_t nt = (size_t)n * T;
+size_t tile_lds_bytes(int rows, int T, int acc_bytes) {
+  const size_t nt = (size_t)rows * T;
   const size_t slots = 2 * (T >= 2 ? 3 : 1) * (size_t)kWave * 8;  // two sets of objective slots
-  return (nt * 4 + 7) / 8 * 8 + (nt * acc_bytes + 7) / 8 * 8 + slots + 4 * kMaxSegments + (size_t)T * 8;
+  return (nt * 4 + 15) / 16 * 16 + (nt * acc_bytes + 7) / 8 * 8 + slots + 4 * kMaxSegments + (size_t)T * 8;
 }
+
+// rows of the on-chip state: the variables and the pad rows
+int state_rows(const pcls_problem* p) { return p->n + p->n_pad; }
 
 struct Launch {
   int logT;
@@ -1645,7 +1643,7 @@ bool auto_acc64(const pcls_problem* p, size_t cap) {
   if (p->acc_bits == 64) return true;
   if (p->acc_bits == 32) return false;
   if (p->s_g32 >= kAcc32MinScale) return false;
-  return tile_lds_bytes(p->n, std::max(1, p->tile_restarts), 8) <= cap;
+  return tile_lds_bytes(state_rows(p), std::max(1, p->tile_restarts), 8) <= cap;
 }
 
 int32_t choose_launch(const pcls_problem* p, int R, Launch& L) {
@@ -1669,13 +1667,13 @@ int32_t choose_launch(const pcls_problem* p, int R, Launch& L) {
     // fewer variables (fewer bank conflicts)
     T = 1;
     const int want_tiles = std::max(1, lim.n_cu);
-    while (T * 2 <= tmax_group && tile_lds_bytes(p->n, T * 2, ab) <= cap && R_pad / (T * 2) >= want_tiles) T *= 2;
+    while (T * 2 <= tmax_group && tile_lds_bytes(state_rows(p), T * 2, ab) <= cap && R_pad / (T * 2) >= want_tiles) T *= 2;
   }
   if (T < 1 || T > 64 || (T & (T - 1)))
     return set_error(PCLS_E_INVALID, "tile_restarts %d must be a power of two in [1, 64]", T);
   if (T > tmax_group)
     return set_error(PCLS_E_UNSUPPORTED, "tile_restarts %d too large for constraints of %d literals", T, p->max_k);
-  const size_t lds = tile_lds_bytes(p->n, T, ab);
+  const size_t lds = tile_lds_bytes(state_rows(p), T, ab);
   if (lds > cap)
     return set_error(PCLS_E_UNSUPPORTED,
                      "state of %d variables x %d restarts needs %zu bytes of LDS (device limit %d)", p->n, T, lds,
@@ -1801,7 +1799,7 @@ int32_t batch_configure(BatchState& b, const pcls_batch_config& cfg_in, hipStrea
   if (cfg.accumulator_bits == 0) {
     bool fits64 = true, asked64 = false, needs64 = false;
     for (const pcls_problem* p : b.probs) {
-      if (tile_lds_bytes(p->n, 1, 8) > budget) fits64 = false;
+      if (tile_lds_bytes(state_rows(p), 1, 8) > budget) fits64 = false;
       if (p->acc_bits == 64) asked64 = true;
       if (p->acc_bits == 0 && p->s_g32 < kAcc32MinScale) needs64 = true;
     }
@@ -1819,7 +1817,7 @@ int32_t batch_configure(BatchState& b, const pcls_batch_config& cfg_in, hipStrea
   std::vector<Cost> work;
   for (size_t i = 0; i < b.probs.size(); ++i) {
     const pcls_problem* p = b.probs[i];
-    if (tile_lds_bytes(p->n, 1, ab) > budget)
+    if (tile_lds_bytes(state_rows(p), 1, ab) > budget)
       return set_error(PCLS_E_UNSUPPORTED, "instance %zu (%d variables) does not fit the LDS budget of %zu bytes", i,
                        p->n, budget);
     if (!acc64 && p->s_g32 < 8)
@@ -1828,10 +1826,10 @@ int32_t batch_configure(BatchState& b, const pcls_batch_config& cfg_in, hipStrea
     const int R_pad = round_up64(b.R[i]);
     const int tmax_group = kWave / std::max(1, p->max_group);
     int T = 1;
-    while (T * 2 <= tmax_group && T * 2 <= R_pad && tile_lds_bytes(p->n, T * 2, ab) <= budget) T *= 2;
+    while (T * 2 <= tmax_group && T * 2 <= R_pad && tile_lds_bytes(state_rows(p), T * 2, ab) <= budget) T *= 2;
     int logT = 0;
     while ((1 << logT) < T) ++logT;
-    lds = std::max(lds, tile_lds_bytes(p->n, T, ab));
+    lds = std::max(lds, tile_lds_bytes(state_rows(p), T, ab));
     for (int r0 = 0; r0 < b.R[i]; r0 += T)
       work.push_back({(double)p->L * T + (double)p->n * T, BatchItem{(int)i, r0, logT, 0}});
     BatchInst& I = b.inst[i];
@@ -1932,7 +1930,7 @@ int32_t grad_stats_launch(const pcls_problem* p, int32_t R, const float* d_x, un
   DeviceLimits lim;
   int32_t st = device_limits(lim);
   if (st != PCLS_OK) return st;
-  const size_t lds = (size_t)((p->n + 1) & ~1) * 4 + 4 * kMaxSegments;
+  const size_t lds = (size_t)((state_rows(p) + 1) & ~1) * 4 + 4 * kMaxSegments;
   if (lds > (size_t)lim.lds_max)
     return set_error(PCLS_E_UNSUPPORTED, "state of %d variables does not fit in LDS", p->n);
   // every term is at most 1, so a constraint's sum over R restarts is at most R k
@@ -2017,7 +2015,7 @@ int32_t pcls_problem_info(const pcls_problem* p, pcls_info* info) {
   info->tile_restarts = p->tile_restarts;
   info->block_threads = p->block_threads;
   info->workspace_bytes = p->image.size();
-  info->lds_bytes_per_restart = (size_t)p->n * 2 * sizeof(float);
+  info->lds_bytes_per_restart = (size_t)state_rows(p) * 2 * sizeof(float);
   for (int32_t c : p->c_cls) ++info->cons_by_kind[p->classes[(size_t)c].kind];
   clear_error();
   return PCLS_OK;
@@ -2035,6 +2033,7 @@ int32_t pcls_upload(pcls_problem* p, void* d_ws, size_t bytes, void* stream) {
   uint8_t* b = (uint8_t*)d_ws;
   ProblemDev& D = p->dev;
   D.n = p->n;
+  D.n_pad = p->n_pad;
   D.m = p->m;
   D.L = (int32_t)p->L;
   D.n_segments = (int32_t)p->segments.size();
@@ -2218,7 +2217,7 @@ int32_t pcls_set_launch(pcls_problem* p, int32_t tile_restarts, int32_t block_th
   if (tile_restarts > 0 && tile_restarts * p->max_group > kWave)
     return set_error(PCLS_E_UNSUPPORTED, "tile_restarts %d too large for constraints of %d literals", tile_restarts,
                      p->max_k);
-  if (tile_restarts > 0 && tile_lds_bytes(p->n, tile_restarts, p->acc_bits == 64 ? 8 : 4) > (size_t)160 * 1024)
+  if (tile_restarts > 0 && tile_lds_bytes(state_rows(p), tile_restarts, p->acc_bits == 64 ? 8 : 4) > (size_t)160 * 1024)
     return set_error(PCLS_E_UNSUPPORTED, "tile of %d restarts x %d variables exceeds LDS", tile_restarts, p->n);
   p->tile_restarts = tile_restarts;
   p->block_threads = block_threads;

@@ -201,6 +201,13 @@ static int pmf_window(const std::vector<int>& sp, float* d, float* h, int nd = k
   return w;
 }
 
+// Whether a long PMF class counts false literals (h = -1/2 in its record).
+static bool pmf_counts_false_of(const std::vector<NodeRec>& nodes, const ClassRec& C) {
+  float rec[24];
+  std::memcpy(rec, &nodes[(size_t)C.node_off], sizeof rec);
+  return rec[16] < 0.f;
+}
+
 // Inverse-DFT weights over the K = k + 1 roots of unity.  With
 // Q_m = prod_i (alpha_m + beta_m y_i), alpha_m = (1 + w^m)/2, beta_m = (1 - w^m)/2,
 // w = exp(2 pi i / K), Q_m is the characteristic function of T at 2 pi m / K,
@@ -233,13 +240,21 @@ static void dft_weights(const std::vector<int>& sp, ClassRec& C, std::vector<Nod
     chat(m, wr, wi);
     double ang = two_pi * (double)m / (double)K;
     double er = std::cos(ang), ei = std::sin(ang);
-    double ar = 0.5 * (1.0 + er), ai = 0.5 * ei;
-    double br = 0.5 * (1.0 - er), bi = -0.5 * ei;
+    // alpha + beta = 1 exactly in float32 (the larger real part is rounded, the
+    // other is 1 minus it, exact by Sterbenz), so a pad slot (y = 1) has the
+    // factor 1 + 0i exactly
+    float far = (float)(0.5 * (1.0 + er)), fbr = (float)(0.5 * (1.0 - er));
+    if (far >= 0.5f)
+      fbr = 1.0f - far;
+    else
+      far = 1.0f - fbr;
+    const float fai = (float)(0.5 * ei);
+    const double ar = far, br = fbr, ai = fai, bi = -(double)fai;
     NodeRec nd;
-    nd.ar = (float)ar;
-    nd.ai = (float)ai;
-    nd.br = (float)br;
-    nd.bi = (float)bi;
+    nd.ar = far;
+    nd.ai = fai;
+    nd.br = fbr;
+    nd.bi = -fai;
     nd.wr = (float)(2.0 * wr);
     nd.wi = (float)(2.0 * wi);
     nd.gr = (float)(2.0 * (wr * br - wi * bi));
@@ -481,8 +496,6 @@ int32_t build_plan(int32_t n, int32_t m, const int32_t* row_ptr, const int32_t* 
     S.c_count = e - j;
     const int kmax = kBucketKmax[b];
     S.lit_base = (int32_t)P->litT.size();
-    // slots past a constraint's length hold -1, so kernels can load a whole
-    // column without first reading the length
     P->litT.resize(P->litT.size() + (size_t)kmax * S.c_count, -1);
     for (int q = 0; q < S.c_count; ++q) {
       int cj = j + q;
@@ -492,6 +505,13 @@ int32_t build_plan(int32_t n, int32_t m, const int32_t* row_ptr, const int32_t* 
         const uint32_t code = (uint32_t)P->lit[P->row_ptr[cj] + i];
         P->litT[(size_t)S.lit_base + (size_t)i * S.c_count + q] = (int32_t)((code >> 1) | ((code & 1u) << 31));
       }
+      // slots past the constraint's length code a pad row (x = +1) with the sign
+      // that makes the slot's factor exactly 1: y = -1 for the product node
+      // (1 - y)/2 and for counts of false literals (h < 0), y = +1 otherwise
+      const ClassRec& C = P->classes[P->c_cls[cj]];
+      const bool neg = (C.kind == KIND_PROD1 && C.b < 0.f) || (C.kind == KIND_PMF && (C.k > kPmfMaxK && pmf_counts_false_of(P->nodes, C)));
+      const uint32_t pad = (uint32_t)(n + q % kPadRows) | (neg ? 0x80000000u : 0u);
+      for (int i = P->c_k[cj]; i < kmax; ++i) P->litT[(size_t)S.lit_base + (size_t)i * S.c_count + q] = (int32_t)pad;
     }
     const int G = group_size(S.kind, kmax);
     P->max_group = std::max(P->max_group, G);
@@ -499,6 +519,7 @@ int32_t build_plan(int32_t n, int32_t m, const int32_t* row_ptr, const int32_t* 
     P->segments.push_back(S);
     j = e;
   }
+  P->n_pad = P->max_bucket > kMaxbShort ? kPadRows : 0;
 
   // ---- heaviest segments first (work per constraint), so that the light items
   // claimed last fill the gaps between waves

@@ -26,6 +26,7 @@ struct pcls_problem {
   std::vector<int32_t> occ;            // per variable: occurrences in non-constant constraints
   int32_t max_group = 1;               // largest lane group G over the segments
   int32_t max_bucket = -1;             // largest length bucket over the segments
+  int32_t n_pad = 0;                   // pad rows of the on-chip state (kPadRows when max_bucket > 8)
   float f_const = 0.f;
   int32_t unit_weights = 1;
 
