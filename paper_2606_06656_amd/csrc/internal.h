@@ -19,7 +19,7 @@ namespace pcls {
 //   DFT   - the K = k+1 complex roots of unity: FE = sum_m chat_m prod_i(alpha_m + beta_m y_i)
 //   PMF   - sp constant outside a window of w counts at one end (thresholds,
 //           at-most-one, exactly-kappa near an end), w <= 4 for k <= 8 (one lane
-//           per pair) and w <= KMAX/2 of the length bucket for 8 < k <= 32 (lane
+//           per pair) and w <= KMAX/2 of the length bucket for 8 < k <= 48 (lane
 //           groups): with C the number of true literals (or of false ones),
 //           FE = c0 + sum_{c < w} d_c Pr[C = c], from a truncated Poisson-binomial
 //           recursion and its adjoint (no products of complex factors)
@@ -28,7 +28,7 @@ enum Kind : int32_t { KIND_PROD1 = 0, KIND_PROD2 = 1, KIND_DFT = 2, KIND_PMF = 3
 constexpr int kNumKinds = 5;
 constexpr int kPmfWindow = 4;  // counts kept by the PMF kind, one lane per pair (k <= 8)
 constexpr int kPmfMaxK = 8;    // longest constraint of the one-lane PMF kind
-constexpr int kPmfGroupMaxK = 32;  // longest constraint of the lane-group PMF kind (window <= bucket / 2)
+constexpr int kPmfGroupMaxK = 48;  // longest constraint of the lane-group PMF kind (window <= bucket / 2)
 
 // Length buckets of the segment kernels: literals per constraint padded to KMAX,
 // processed by groups of G lanes holding J = KMAX / G literals each.
@@ -97,8 +97,9 @@ struct ClassRec {
 // and 2*chat_m*beta_m for the gradient (the 2 covers the conjugate node K - m).
 // A PMF class of k <= 8 literals has one record: {d_0, d_1, d_2, d_3, h, 0, 0, 0},
 // where the counted event of literal i has probability 1/2 - h y_i (h = 1/2:
-// true, -1/2: false); a longer one has three records read as 24 floats:
-// d_0..d_15 (zero past its window), h, then padding.
+// true, -1/2: false); a longer one has five records read as 40 floats:
+// d_0..d_31 (zero past its window), h, a threshold flag (d constant on the
+// window), then padding.
 struct NodeRec {
   float ar, ai, br, bi;
   float wr, wi, gr, gi;

@@ -605,7 +605,9 @@ __device__ __forceinline__ void count_adjoint(const float* pi, const float (&pre
 // from DA (or DB).  Every step adds products of probabilities: no
 // cancellation, and about (J + W) operations per literal against about 14 per
 // node and literal (k/2 nodes) on the DFT path.
-// Class data: node table entry floats 0..15 hold d_0..d_15, float 16 holds h.
+// Class data (node table entries read as floats): d_0..d_31 (zero past the
+// window), h at 32, and at 33 a flag for threshold windows (d constant on the
+// window [0, w), w the class's window).
 template <int KMAX, int G, class SK>
 __device__ __forceinline__ void pmfg_pair(const ProblemDev& P, int cls, const Fetched<KMAX / G>& fp, int lig, int t,
                                           int logT, const float* xs, SK& sink, float& fchunk, float gsc, float fsc) {
@@ -614,7 +616,7 @@ __device__ __forceinline__ void pmfg_pair(const ProblemDev& P, int cls, const Fe
   constexpr int MH = H + 1;                   // counts of a half (never truncated: H + 1 <= W)
   constexpr int W = KMAX / 2;                 // widest window of the bucket
   constexpr int WL = J + 1 < W ? J + 1 : W;   // counts of one lane kept
-  static_assert(G == 2 || G == 4, "lane groups of 2 or 4");
+  static_assert(G == 2 || G == 4, "lane groups of 2 or 4 (8: pmfg8_pair)");
   static_assert(J % 2 == 0 && MH <= W, "halves");
   const int T = 1 << logT;
   kptr<ClassRec> classes = kconst(P.classes);
@@ -622,7 +624,7 @@ __device__ __forceinline__ void pmfg_pair(const ProblemDev& P, int cls, const Fe
   float d[W];
 #pragma unroll
   for (int c = 0; c < W; ++c) d[c] = dt[c];
-  const float h = dt[16];
+  const float h = dt[32];
 
   float pi[J];
 #pragma unroll
@@ -709,6 +711,188 @@ __device__ __forceinline__ void pmfg_pair(const ProblemDev& P, int cls, const Fe
   if (lig == 0) fchunk = fmaf(fp.w * fsc, fe, fchunk);
 
   // dFE/dy_j = -h dFE/dpi_j
+  float gp[J];
+  count_adjoint<H, MH>(pi, prea, DA, gp);
+  count_adjoint<H, MH>(pi + H, preb, DB, gp + H);
+  const float coef = -h * (fp.w * gsc);
+#pragma unroll
+  for (int j = J - 1; j >= 0; --j)
+    sink.add(lit_off(fp.code[j], logT, t), flip(coef * gp[j], lit_sign(fp.code[j])), fp.code[j]);
+}
+
+// Count distribution of N literals (probabilities pi), truncated to M counts,
+// without keeping the intermediate distributions.
+template <int N, int M>
+__device__ __forceinline__ void count_only(const float* pi, float (&q)[M]) {
+  q[0] = 1.f;
+#pragma unroll
+  for (int c = 1; c < M; ++c) q[c] = 0.f;
+#pragma unroll
+  for (int j = 0; j < N; ++j) {
+#pragma unroll
+    for (int c = M - 1; c >= 1; --c)
+      if (c <= j + 1) q[c] = fmaf(pi[j], q[c - 1] - q[c], q[c]);
+    q[0] = fmaf(-pi[j], q[0], q[0]);
+  }
+}
+
+// Truncated convolution r = (u * v) restricted to counts < NR.
+template <int NU, int NV, int NR>
+__device__ __forceinline__ void conv_trunc(const float (&u)[NU], const float (&v)[NV], float (&r)[NR]) {
+#pragma unroll
+  for (int c = 0; c < NR; ++c) {
+    float acc = 0.f;
+#pragma unroll
+    for (int a = 0; a < NU; ++a)
+      if (c - a >= 0 && c - a < NV) acc = fmaf(u[a], v[c - a], acc);
+    r[c] = acc;
+  }
+}
+
+// The lane at xor distance 4 T in the lane's group of eight.  With T = 1 the
+// group is an 8-lane half-row: the lower quad reads 4 lanes up, the upper quad 4
+// lanes down (two DPP row shifts and a select); otherwise a wave shuffle.  The
+// partner is the same lane either way, so results do not depend on T (the four
+// lanes of a quad hold totals summed in different orders, which may differ in
+// the last bit).
+template <int N>
+__device__ __forceinline__ void other_quad(const float (&src)[N], float (&dst)[N], int T, int lig) {
+  if (T == 1) {
+    const bool upper = (lig & 4) != 0;
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+      const float up = row_shl<4>(src[i]), dn = row_shr<4>(src[i]);
+      dst[i] = upper ? dn : up;
+    }
+  } else {
+#pragma unroll
+    for (int i = 0; i < N; ++i) dst[i] = __shfl_xor(src[i], 4 * T);
+  }
+}
+
+// PMF kind for 33 to 48 literals (lane groups of G = 8, J = KMAX/8 literals per
+// lane, window up to W = KMAX/2 counts): as pmfg_pair with one more level of the
+// butterfly, the other quad's total z4.  E = x1 * z2 * z4 is not formed; with
+// R4(j) = sum_b d_{j+b} z4(b) and R2(j) = sum_a z2(a) R4(j+a),
+// D(c) = sum_a x1(a) R2(c+a).  For a threshold window (d = d_0 on [0, w)),
+// R4(j) = d_0 S(w - j), S(m) the sum of z4 below m, read at the wave-uniform
+// offset W - w by a barrel shift of uniform branches instead of the W^2/2
+// products of the general correlation.  To stay within the register budget the
+// lane's local distributions are computed twice: once without their
+// intermediate distributions for the butterfly, then with them for the adjoint.
+template <int KMAX, class SK>
+__device__ __forceinline__ void pmfg8_pair(const ProblemDev& P, int cls, const Fetched<KMAX / 8>& fp, int lig,
+                                           int t, int logT, const float* xs, SK& sink, float& fchunk, float gsc,
+                                           float fsc) {
+  constexpr int J = KMAX / 8;
+  constexpr int H = J / 2;
+  constexpr int MH = H + 1;
+  constexpr int W = KMAX / 2;
+  constexpr int WL = J + 1;            // counts of one lane (J + 1 <= W)
+  constexpr int W2 = 2 * WL - 1;       // counts of a pair (2 J + 1 <= W)
+  static_assert(J % 2 == 0 && W2 <= W, "shape");
+  const int T = 1 << logT;
+  kptr<ClassRec> classes = kconst(P.classes);
+  kptr<float> dt = reinterpret_cast<kptr<float>>(kconst(P.nodes) + classes[cls].node_off);
+  const int w = classes[cls].nyquist;
+  const float h = dt[32];
+  const bool thr = dt[33] != 0.f;
+
+  float pi[J];
+#pragma unroll
+  for (int j = 0; j < J; ++j)
+    pi[j] = fmaf(-h, flip(x_at(xs, lit_off(fp.code[j], logT, t)), lit_sign(fp.code[j])), 0.5f);
+
+  // butterfly over the group: D(c) for the lane's local count c < WL
+  float D[WL];
+  {
+    float x1[WL];
+    {
+      float qa[MH], qb[MH], q[WL];
+      count_only<H, MH>(pi, qa);
+      count_only<H, MH>(pi + H, qb);
+      conv_trunc(qa, qb, q);
+      xor_exchange(q, x1, T);
+      float y2[W2];
+      conv_trunc(q, x1, y2);
+      float z2[W2];
+      xor_exchange(y2, z2, 2 * T);
+      float R4[W];
+      {
+        float y4[W];
+        conv_trunc(y2, z2, y4);
+        float z4[W];
+        other_quad(y4, z4, T, lig);
+        if (thr) {
+          // A(i) = sum_{b < W - i} z4(b), then shifted left by W - w: A(j) -> S(w - j)
+          float A[W];
+          float run = 0.f;
+#pragma unroll
+          for (int i = W - 1; i >= 0; --i) {
+            run += z4[W - 1 - i];
+            A[i] = run;
+          }
+          const int sft = W - w;  // wave-uniform, 0 <= sft < W
+#pragma unroll
+          for (int k = 1; k < W; k <<= 1) {
+            if (sft & k) {
+#pragma unroll
+              for (int i = 0; i < W; ++i) A[i] = i + k < W ? A[i + k] : 0.f;
+            }
+          }
+          const float d0 = dt[0];
+#pragma unroll
+          for (int j = 0; j < W; ++j) R4[j] = d0 * A[j];
+        } else {
+#pragma unroll
+          for (int j = 0; j < W; ++j) {
+            float acc = 0.f;
+#pragma unroll
+            for (int b = 0; b < W; ++b)
+              if (j + b < W) acc = fmaf(dt[j + b], z4[b], acc);
+            R4[j] = acc;
+          }
+        }
+      }
+      float R2[W2];
+#pragma unroll
+      for (int j = 0; j < W2; ++j) {
+        float acc = 0.f;
+#pragma unroll
+        for (int a = 0; a < W2; ++a)
+          if (j + a < W) acc = fmaf(z2[a], R4[j + a], acc);
+        R2[j] = acc;
+      }
+#pragma unroll
+      for (int c = 0; c < WL; ++c) {
+        float acc = 0.f;
+#pragma unroll
+        for (int a = 0; a < WL; ++a) acc = fmaf(x1[a], R2[c + a], acc);
+        D[c] = acc;
+      }
+    }
+  }
+
+  // the lane's halves again, with their intermediate distributions
+  float prea[H][MH], preb[H][MH], qa[MH], qb[MH];
+  count_forward<H, MH>(pi, prea, qa);
+  count_forward<H, MH>(pi + H, preb, qb);
+  float DA[MH], DB[MH];
+#pragma unroll
+  for (int a = 0; a < MH; ++a) {
+    float sa = 0.f, sb = 0.f;
+#pragma unroll
+    for (int b = 0; b < MH; ++b) {
+      sa = fmaf(qb[b], D[a + b], sa);
+      sb = fmaf(qa[b], D[a + b], sb);
+    }
+    DA[a] = sa;
+    DB[a] = sb;
+  }
+  float fe = 0.f;
+#pragma unroll
+  for (int a = 0; a < MH; ++a) fe = fmaf(qa[a], DA[a], fe);
+  if (lig == 0) fchunk = fmaf(fp.w * fsc, fe, fchunk);
   float gp[J];
   count_adjoint<H, MH>(pi, prea, DA, gp);
   count_adjoint<H, MH>(pi + H, preb, DB, gp + H);
@@ -958,6 +1142,8 @@ __device__ __forceinline__ void run_segment(const ProblemDev& P, const Segment& 
               if constexpr (KIND == KIND_DFT) {
                 kptr<ClassRec> cr = kconst(P.classes);
                 dft_pair<KMAX, G>(P, cr[cc].n_nodes, cc, f, lig, t, logT, xs, sink, fchunk, gsc, fsc);
+              } else if constexpr (G == 8) {
+                pmfg8_pair<KMAX>(P, cc, f, lig, t, logT, xs, sink, fchunk, gsc, fsc);
               } else {
                 pmfg_pair<KMAX, G>(P, cc, f, lig, t, logT, xs, sink, fchunk, gsc, fsc);
               }
@@ -1039,7 +1225,8 @@ __device__ __forceinline__ void run_segment(const ProblemDev& P, const Segment& 
   X(KIND, 8, 12)                         \
   X(KIND, 9, 16)                         \
   X(KIND, 10, 24)                        \
-  X(KIND, 11, 32)
+  X(KIND, 11, 32)                        \
+  X(KIND, 12, 48)
 
 #define PCLS_CASE(KIND, B, KMAX)                                                                    \
   case (KIND)*kNumBuckets + (B):                                                                    \

@@ -203,9 +203,9 @@ static int pmf_window(const std::vector<int>& sp, float* d, float* h, int nd = k
 
 // Whether a long PMF class counts false literals (h = -1/2 in its record).
 static bool pmf_counts_false_of(const std::vector<NodeRec>& nodes, const ClassRec& C) {
-  float rec[24];
+  float rec[40];
   std::memcpy(rec, &nodes[(size_t)C.node_off], sizeof rec);
-  return rec[16] < 0.f;
+  return rec[32] < 0.f;
 }
 
 // Inverse-DFT weights over the K = k + 1 roots of unity.  With
@@ -355,15 +355,20 @@ int32_t build_plan(int32_t n, int32_t m, const int32_t* row_ptr, const int32_t* 
         C.n_nodes = 1;
         P->nodes.push_back(N);
       } else if (C.kind == KIND_PMF) {
-        // lane-group PMF: d_0..d_15 then h, in three node records
-        float rec[24] = {};
+        // lane-group PMF: d_0..d_31, h, threshold flag, in five node records
+        float rec[40] = {};
         float h;
-        C.nyquist = pmf_window(sp, rec, &h, 16);
-        rec[16] = h;
+        const int w = pmf_window(sp, rec, &h, 32);
+        C.nyquist = w;
+        rec[32] = h;
+        bool thr = true;  // d constant on the window
+        for (int c = 1; c < w; ++c)
+          if (rec[c] != rec[0]) thr = false;
+        rec[33] = thr ? 1.f : 0.f;
         C.c0 = (float)(h > 0.f ? sp[k] : sp[0]);
         C.node_off = (int32_t)P->nodes.size();
-        C.n_nodes = 3;
-        for (int r = 0; r < 3; ++r) {
+        C.n_nodes = 5;
+        for (int r = 0; r < 5; ++r) {
           NodeRec N;
           std::memcpy(&N, rec + 8 * r, sizeof N);
           P->nodes.push_back(N);

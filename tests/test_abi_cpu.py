@@ -138,8 +138,8 @@ def _expected_kind(sp):
     """Evaluation path the planner should pick for a spectrum (sp_t = -1 when the
     constraint holds with t true literals): a product form when one exists, the
     count window when the spectrum is constant past w counts at one end with
-    w <= 4 for k <= 8, or w <= half the length bucket (12, 16, 24, 32) for
-    8 < k <= 32, else the DFT."""
+    w <= 4 for k <= 8, or w <= half the length bucket (12, 16, 24, 32, 48)
+    for 8 < k <= 48, else the DFT."""
     k = len(sp) - 1
     if all(v == sp[0] for v in sp):
         return "const"
@@ -153,13 +153,13 @@ def _expected_kind(sp):
     wf = max([f + 1 for f in range(k + 1) if sp[k - f] != sp[0]], default=0)
     if k <= 8 and min(wt, wf) <= 4:
         return "pmf"
-    bucket = next(b for b in (12, 16, 24, 32, 10 ** 9) if k <= b)
-    if 8 < k <= 32 and 2 * min(wt, wf) <= bucket:
+    bucket = next(b for b in (12, 16, 24, 32, 48, 10 ** 9) if k <= b)
+    if 8 < k <= 48 and 2 * min(wt, wf) <= bucket:
         return "pmf"
     return "dft"
 
 
-@pytest.mark.parametrize("k", list(range(1, 18)) + [23, 24, 25, 31, 32, 33])
+@pytest.mark.parametrize("k", list(range(1, 18)) + [23, 24, 25, 31, 32, 33, 47, 48, 49, 63, 64, 65])
 def test_plan_picks_evaluation_path(k):
     from oracle import coeffs as C
     for ctype in (C.OR, C.XOR, C.CARD_GE, C.NAE, C.EO, C.AMO, C.EK):
