@@ -16,7 +16,7 @@ of K steps (inputs resident in HBM), timed with HIP events on the stream the
 library launches on.  Printed as one JSON line with
 
 - `roofline`: the binding resource of the dominant kernel, VALU issue (the
-  fraction of SIMD cycles with a vector instruction being worked on, from the
+  fraction of SIMD quad-cycles that issue a vector instruction, from the
   committed rocprofv3 counters of the same launch, over the live launch time),
   with the measured HBM traffic of the launch;
 - `gather_model`: the throughput normalised by the algorithmic bytes of an
@@ -108,12 +108,14 @@ def gather_model(alg_bytes_per_launch: float, launch_ms: float):
 
 
 def roofline(kernel: str, key: str, alg_bytes_per_launch: float, launch_ms: float, steps_per_launch: int):
-    """Binding resource of the dominant kernel: VALU issue.  achieved = SIMD
-    cycles with a VALU instruction in flight per launch (SQ_ACTIVE_INST_VALU,
-    quad-cycles x 4, from the committed profile of this kernel source) over the
-    live launch time; peak = every SIMD busy every cycle.  traffic = HBM bytes
-    per launch from the FETCH_SIZE / WRITE_SIZE passes."""
-    out = {"bound": "alu", "resource": "VALU issue (SIMD cycles working on a vector instruction)",
+    """Binding resource of the dominant kernel: VALU issue.  A SIMD issues a
+    wave64 vector instruction per quad-cycle (two in a dual-issue quad-cycle);
+    achieved = the quad-cycles with an issue per launch, SQ_INSTS_VALU minus
+    SQ_ACTIVE_INST_VALU2 (from the committed profile of this kernel source),
+    times 4 cycles, over the live launch time; peak = every SIMD issuing every
+    quad-cycle (256 CUs x 4 SIMDs x 2.4 GHz).  traffic = HBM bytes per launch
+    from the FETCH_SIZE / WRITE_SIZE passes."""
+    out = {"bound": "alu", "resource": "VALU issue slots (SIMD cycles of quad-cycles issuing a vector instruction)",
            "achieved": None, "peak": VALU_PEAK_GSIMDCYC, "unit": "G SIMD-cycles/s", "frac": None,
            "traffic": None, "kernel": kernel, "launch_ms": launch_ms, "steps_per_launch": steps_per_launch}
     rec = profile_record(kernel, key)
@@ -194,16 +196,25 @@ def cpu_baseline_all_cores(op, inst, lr: float, budget_s: float, R_sample: int):
             "sample": f"{P} threads x {R_sample} restarts, {steps} steps in total, {el:.1f} s"}
 
 
-def time_resident(inst, R, lr, steps, warmup, S, tile=0, block=0):
+def tuned_or_fixed(inst, R, lr, args):
+    """The problem planned and launched as the autotuner chose (cached by the
+    workload's signature), or with the launch given on the command line."""
+    from paper_2606_06656_amd import autotune, pcls
+
+    if args.tile or args.block or args.no_tune:
+        prob = pcls.Problem.from_instance(inst, device="cuda:0")
+        if args.tile or args.block:
+            prob.set_launch(args.tile, args.block)
+        return prob, None
+    rec = autotune.tune_problem(inst, R, lr, cache_path=args.tune_cache)
+    return autotune.tuned_problem(inst, R, rec), rec
+
+
+def time_resident(prob, R, lr, steps, warmup, S):
     """Equal launches of the resident engine, S steps each (warm-up launches of
     the same size first), timed with HIP events on the library's stream."""
     import torch
 
-    from paper_2606_06656_amd import pcls
-
-    prob = pcls.Problem.from_instance(inst, device="cuda:0")
-    if tile or block:
-        prob.set_launch(tile, block)
     X = prob.new_state(R)
     prob.init_restarts(X, R, 2)
     stream = torch.cuda.current_stream()
@@ -229,7 +240,8 @@ def time_resident(inst, R, lr, steps, warmup, S, tile=0, block=0):
 def bench_resident(name, args, with_cpu=True):
     inst, R, lr, key = workload(name)
     S = args.steps_per_launch or DEFAULT_STEPS_PER_LAUNCH[name]
-    t = time_resident(inst, R, lr, args.steps, args.warmup, S, args.tile, args.block)
+    prob, tune = tuned_or_fixed(inst, R, lr, args)
+    t = time_resident(prob, R, lr, args.steps, args.warmup, S)
     ms, steps, S = t["ms"], t["steps"], t["S"]
     value = R * inst.L * steps / (ms / 1e3)
     alg = algorithmic_bytes_per_step(inst.n, inst.m, inst.L, R) * S
@@ -238,7 +250,8 @@ def bench_resident(name, args, with_cpu=True):
         "warmup": args.warmup, "ms_per_step": ms / steps, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": key, "n": inst.n, "m": inst.m, "L": inst.L, "restarts": R, "lr": lr,
-                   "steps_per_launch": S, "launch": t["launch"]},
+                   "steps_per_launch": S, "launch": t["launch"], "bucket_table": prob.info().bucket_table,
+                   "autotune": tune},
         "objective_last_step": t["objective_last_step"],
         "roofline": roofline("tile_kernel", key, alg, ms / t["n_launch"], S),
         "gather_model": gather_model(alg, ms / t["n_launch"]),
@@ -251,39 +264,19 @@ def bench_resident(name, args, with_cpu=True):
 def bench_c2_extra(args):
     """The mixed n = 2000 instance (1024 restarts, 100 steps per launch)."""
     inst, R, lr, key = workload("c2")
-    t = time_resident(inst, R, lr, 200, 100, 100)
+    prob, tune = tuned_or_fixed(inst, R, lr, args)
+    t = time_resident(prob, R, lr, 200, 100, 100)
     value = R * inst.L * t["steps"] / (t["ms"] / 1e3)
     alg = algorithmic_bytes_per_step(inst.n, inst.m, inst.L, R) * t["S"]
     return {"workload": key, "value": value, "unit": "literal-evals/s", "steps": t["steps"],
-            "ms_per_step": t["ms"] / t["steps"], "launch": t["launch"],
+            "ms_per_step": t["ms"] / t["steps"], "launch": t["launch"], "autotune": tune,
             "gather_model": gather_model(alg, t["ms"] / t["n_launch"])}
 
 
-def bench_batch(args, insts, R, lr, key, steps=None, warmup=None):
-    """Many uneven instances: one persistent launch per captured graph replay
-    (configuration from the autotuner) against per-instance plain launches."""
+def _time_graph(b, lr, S, reps, warmup_reps):
     import torch
-
-    from paper_2606_06656_amd import pcls
-    from paper_2606_06656_amd.batch import Batch
-
-    steps = args.steps if steps is None else steps
-    warmup = args.warmup if warmup is None else warmup
-    probs = [pcls.Problem.from_instance(i, device="cuda:0") for i in insts]
-    states = []
-    for k, p in enumerate(probs):
-        X = p.new_state(R)
-        p.init_restarts(X, R, 4000 + k)
-        states.append(X)
-    S = max(1, min(args.graph_steps, steps))
-    # every step writes each restart's objective (obj + grad per step)
-    traces = [torch.empty((S, R), dtype=torch.float32, device="cuda:0") for _ in probs]
-    b = Batch(probs, [R] * len(probs), states, traces)
-    tune = b.autotune(lr, probe_steps=3, cache_path=args.tune_cache)
-    reps = max(1, steps // S)
-    steps = reps * S
     b.capture(lr, S)
-    for _ in range(max(1, warmup // S)):
+    for _ in range(warmup_reps):
         b.replay()
     torch.cuda.synchronize()
     stream = torch.cuda.current_stream()
@@ -293,11 +286,53 @@ def bench_batch(args, insts, R, lr, key, steps=None, warmup=None):
         b.replay()
     e1.record(stream)
     torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1)
+    return e0.elapsed_time(e1)
+
+
+def bench_batch(args, insts, R, lr, key, steps=None, warmup=None):
+    """Many uneven instances: one persistent launch per captured graph replay,
+    with the bucket table and configuration the autotuner picked, against the
+    fixed default (every compiled length, 1024 threads, the whole LDS) and
+    against per-instance plain launches."""
+    import torch
+
+    from paper_2606_06656_amd import autotune, pcls
+    from paper_2606_06656_amd.batch import Batch
+
+    steps = args.steps if steps is None else steps
+    warmup = args.warmup if warmup is None else warmup
+    S = max(1, min(args.graph_steps, steps))
+    reps = max(1, steps // S)
+    steps = reps * S
+    tune = autotune.tune_batch(insts, [R] * len(insts), lr, probe_steps=3, cache_path=args.tune_cache)
     L_tot = sum(i.L for i in insts)
+
+    def setup(table):
+        probs = [pcls.Problem.from_instance(i, device="cuda:0", bucket_table=table) for i in insts]
+        states = []
+        for k, p in enumerate(probs):
+            X = p.new_state(R)
+            p.init_restarts(X, R, 4000 + k)
+            states.append(X)
+        # every step writes each restart's objective (obj + grad per step)
+        traces = [torch.empty((S, R), dtype=torch.float32, device="cuda:0") for _ in probs]
+        return probs, states, Batch(probs, [R] * len(probs), states, traces)
+
+    # fixed default configuration
+    probs0, states0, b0 = setup(0)
+    ms_fixed = _time_graph(b0, lr, S, reps, max(1, warmup // S))
+    cfg_fixed = b0.config()
+    b0.close()
+    del probs0, states0
+    # autotuned
+    probs, states, b = setup(tune["bucket_table"])
+    b.set_config(tune["block_threads"], tune["lds_budget"], 0, tune["accumulator_bits"])
+    ms = _time_graph(b, lr, S, reps, max(1, warmup // S))
     value = R * L_tot * steps / (ms / 1e3)
     # per-instance plain launches: one pcls_step(1) per instance per step
     bs = args.baseline_steps
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record(stream)
     for _ in range(bs):
         for p, X in zip(probs, states):
@@ -309,6 +344,9 @@ def bench_batch(args, insts, R, lr, key, steps=None, warmup=None):
     alg = sum(algorithmic_bytes_per_step(i.n, i.m, i.L, R) for i in insts) * S
     return {"value": value, "ms": ms, "steps": steps, "S": S, "reps": reps, "L_tot": L_tot,
             "n_tot": sum(i.n for i in insts), "m_tot": sum(i.m for i in insts), "tune": tune, "cfg": b.config(),
+            "fixed_config": {"value": R * L_tot * steps / (ms_fixed / 1e3), "unit": "literal-evals/s",
+                             "ms_per_step": ms_fixed / steps, "bucket_table": 0, "batch": cfg_fixed,
+                             "speedup_of_tuned": ms_fixed / ms},
             "per_instance_launches": {"value": base_rate, "unit": "literal-evals/s", "steps": bs,
                                       "ms_per_step": ms_b / bs, "launches_per_step": len(insts),
                                       "speedup_of_batched": value / base_rate},
@@ -325,6 +363,7 @@ def bench_c4_line(args):
         "config": {"workload": key, "instances": len(insts), "sum_n": r["n_tot"], "sum_m": r["m_tot"],
                    "sum_L": r["L_tot"], "restarts_each": R, "lr": lr, "graph_steps": r["S"],
                    "autotune": r["tune"], "batch": r["cfg"]},
+        "fixed_config": r["fixed_config"],
         "per_instance_launches": r["per_instance_launches"],
         "roofline": roofline("batch_kernel", key, r["alg"], r["ms"] / r["reps"], r["S"]),
         "gather_model": gather_model(r["alg"], r["ms"] / r["reps"]),
@@ -337,7 +376,7 @@ def bench_c4_extra(args):
     r = bench_batch(args, insts, R, lr, key, steps=100, warmup=50)
     return {"workload": key, "value": r["value"], "unit": "literal-evals/s", "steps": r["steps"],
             "ms_per_step": r["ms"] / r["steps"], "graph_steps": r["S"], "autotune": r["tune"], "batch": r["cfg"],
-            "per_instance_launches": r["per_instance_launches"],
+            "fixed_config": r["fixed_config"], "per_instance_launches": r["per_instance_launches"],
             "gather_model": gather_model(r["alg"], r["ms"] / r["reps"])}
 
 
@@ -389,7 +428,8 @@ def main():
                     help="steps per launch of the resident kernel, timed and warm-up launches alike "
                          "(0 = 10 for c3 / c3long, 100 otherwise)")
     ap.add_argument("--graph-steps", type=int, default=50, help="c4: steps captured per graph replay")
-    ap.add_argument("--tune-cache", default=None, help="c4: autotuner cache file (reused when present)")
+    ap.add_argument("--tune-cache", default=None, help="autotuner cache file (reused when present)")
+    ap.add_argument("--no-tune", action="store_true", help="resident engine: the planner's default launch")
     ap.add_argument("--baseline-steps", type=int, default=10, help="c4: steps of per-instance plain launches")
     ap.add_argument("--tile", type=int, default=0, help="restarts per workgroup (0 = auto)")
     ap.add_argument("--block", type=int, default=0, help="threads per workgroup (0 = auto)")

@@ -74,7 +74,11 @@ typedef struct pcls_plan_options {
                                (grad_scale_log2_32 >= 24: no coarser than FP32 rounding at
                                unit scale), else 64-bit when the state fits on chip, else
                                32-bit */
-  int32_t reserved[6];
+  int32_t bucket_table;     /* length buckets the constraints are padded to: 0 = every
+                               compiled length (1..8, 12, 16, 24, 32, 48, 64, 96, 128, 192,
+                               256), 1 = 1..8 and the powers of two above (fewer segments,
+                               more padding); chosen by the autotuners */
+  int32_t reserved[5];
 } pcls_plan_options;
 
 typedef struct pcls_info {
@@ -92,8 +96,10 @@ typedef struct pcls_info {
   size_t workspace_bytes;
   size_t lds_bytes_per_restart; /* on-chip bytes one restart's state needs */
   int32_t cons_by_kind[5];   /* constraints per evaluation path: one-node product, two-node
-                                product, K-node DFT, truncated count distribution (k <= 8,
-                                window of at most 4 counts), constant */
+                                product, K-node DFT, truncated count distribution (k <= 48,
+                                window of at most 4 counts for k <= 8, at most half the
+                                length bucket above), constant */
+  int32_t bucket_table;      /* length-bucket table of the plan (pcls_plan_options) */
 } pcls_info;
 
 /*

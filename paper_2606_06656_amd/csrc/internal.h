@@ -62,9 +62,17 @@ constexpr int group_size(int kind, int kmax) {
   return (kmax <= 8 || (kind != KIND_DFT && kind != KIND_PMF && kmax <= 16)) ? 1 : lane_groups(kmax);
 }
 
-inline int bucket_of(int k) {
+// Bucket tables: which of the compiled lengths a plan uses.  Table 0 uses all of
+// them; table 1 only the exact ones up to 8 and the powers of two above (fewer
+// segments, more padded slots).  The autotuners choose between them.
+constexpr int kNumBucketTables = 2;
+inline bool bucket_in_table(int b, int table) {
+  const int k = kBucketKmax[b];
+  return table == 0 || k <= 8 || (k & (k - 1)) == 0;
+}
+inline int bucket_of(int k, int table = 0) {
   for (int b = 0; b < kNumBuckets; ++b)
-    if (k <= kBucketKmax[b]) return b;
+    if (k <= kBucketKmax[b] && bucket_in_table(b, table)) return b;
   return -1;
 }
 

@@ -2204,6 +2204,7 @@ int32_t pcls_problem_info(const pcls_problem* p, pcls_info* info) {
   info->workspace_bytes = p->image.size();
   info->lds_bytes_per_restart = (size_t)state_rows(p) * 2 * sizeof(float);
   for (int32_t c : p->c_cls) ++info->cons_by_kind[p->classes[(size_t)c].kind];
+  info->bucket_table = p->bucket_table;
   clear_error();
   return PCLS_OK;
 }

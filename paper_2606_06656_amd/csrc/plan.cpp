@@ -121,7 +121,7 @@ static void bank_aware_order(const int32_t* row_ptr, const int32_t* lit, int k, 
   std::copy(out.begin(), out.end(), run);
 }
 
-static void classify(const std::vector<int>& sp, bool force_generic, ClassRec& C) {
+static void classify(const std::vector<int>& sp, bool force_generic, int table, ClassRec& C) {
   const int k = (int)sp.size() - 1;
   bool all_eq = true, tail_eq = true, head_eq = true, alt = true, mid_eq = true;
   for (int t = 0; t <= k; ++t) {
@@ -172,7 +172,8 @@ static void classify(const std::vector<int>& sp, bool force_generic, ClassRec& C
       return;
     }
     const int w = pmf_window(sp, nullptr, nullptr, 0);
-    if ((k <= kPmfMaxK && w <= kPmfWindow) || (k > kPmfMaxK && k <= kPmfGroupMaxK && 2 * w <= kBucketKmax[bucket_of(k)])) {
+    const int kb = kBucketKmax[bucket_of(k, table)];
+    if ((k <= kPmfMaxK && w <= kPmfWindow) || (k > kPmfMaxK && kb <= kPmfGroupMaxK && 2 * w <= kb)) {
       C.kind = KIND_PMF;
       return;
     }
@@ -293,6 +294,9 @@ int32_t build_plan(int32_t n, int32_t m, const int32_t* row_ptr, const int32_t* 
   const int acc_bits = options ? options->accumulator_bits : 0;
   if (acc_bits != 0 && acc_bits != 32 && acc_bits != 64)
     return set_error(PCLS_E_INVALID, "accumulator_bits must be 0, 32 or 64 (got %d)", acc_bits);
+  const int table = options ? options->bucket_table : 0;
+  if (table < 0 || table >= kNumBucketTables)
+    return set_error(PCLS_E_INVALID, "bucket_table must be 0 or 1 (got %d)", table);
 
   std::vector<int32_t> stamp((size_t)n, -1);
   for (int c = 0; c < m; ++c) {
@@ -323,6 +327,7 @@ int32_t build_plan(int32_t n, int32_t m, const int32_t* row_ptr, const int32_t* 
   P->m = m;
   P->L = L;
   P->force_generic = force_generic ? 1 : 0;
+  P->bucket_table = table;
 
   // ---- classes
   std::map<ClassKey, int> class_of;
@@ -339,7 +344,7 @@ int32_t build_plan(int32_t n, int32_t m, const int32_t* row_ptr, const int32_t* 
       for (int t = 0; t <= k; ++t) sp[t] = holds(ty, k, pr, t) ? -1 : 1;
       ClassRec C{};
       C.k = k;
-      classify(sp, force_generic, C);
+      classify(sp, force_generic, P->bucket_table, C);
       if (C.kind == KIND_DFT) dft_weights(sp, C, P->nodes);
       if (C.kind == KIND_PMF && k <= kPmfMaxK) {
         NodeRec N{};
@@ -431,7 +436,7 @@ int32_t build_plan(int32_t n, int32_t m, const int32_t* row_ptr, const int32_t* 
   auto seg_key = [&](int c) {
     const ClassRec& C = P->classes[cls_orig[c]];
     int kind = C.kind;
-    int b = kind == KIND_CONST ? 0 : bucket_of(C.k);
+    int b = kind == KIND_CONST ? 0 : bucket_of(C.k, P->bucket_table);
     return std::make_tuple(kind, b, cls_orig[c], c);
   };
   std::sort(order.begin(), order.end(), [&](int a, int b) { return seg_key(a) < seg_key(b); });
@@ -442,10 +447,10 @@ int32_t build_plan(int32_t n, int32_t m, const int32_t* row_ptr, const int32_t* 
     for (int a = 0; a < m;) {
       const ClassRec& C = P->classes[cls_orig[order[a]]];
       if (C.kind == KIND_CONST) break;
-      const int b = bucket_of(C.k);
+      const int b = bucket_of(C.k, P->bucket_table);
       if (a > 0) {
         const ClassRec& Cp = P->classes[cls_orig[order[a - 1]]];
-        if (Cp.kind != C.kind || bucket_of(Cp.k) != b) seg_start = a;
+        if (Cp.kind != C.kind || bucket_of(Cp.k, P->bucket_table) != b) seg_start = a;
       }
       int e = a;
       while (e < m && cls_orig[order[e]] == cls_orig[order[a]]) ++e;
@@ -480,7 +485,7 @@ int32_t build_plan(int32_t n, int32_t m, const int32_t* row_ptr, const int32_t* 
   while (j < m) {
     const ClassRec& C0 = P->classes[P->c_cls[j]];
     if (C0.kind == KIND_CONST) break;
-    int b = bucket_of(C0.k);
+    int b = bucket_of(C0.k, P->bucket_table);
     int e = j;
     Segment S{};
     S.kind = C0.kind;
@@ -491,7 +496,7 @@ int32_t build_plan(int32_t n, int32_t m, const int32_t* row_ptr, const int32_t* 
     S.m_max = 0;
     while (e < m) {
       const ClassRec& C = P->classes[P->c_cls[e]];
-      if (C.kind != S.kind || bucket_of(C.k) != b) break;
+      if (C.kind != S.kind || bucket_of(C.k, P->bucket_table) != b) break;
       if (C.k != S.k_fixed) S.k_fixed = 0;
       if (P->c_cls[e] != S.cls_fixed) S.cls_fixed = -1;
       if (C.kind == KIND_DFT) S.m_max = std::max(S.m_max, C.n_nodes);

@@ -27,6 +27,7 @@ struct pcls_problem {
   int32_t max_group = 1;               // largest lane group G over the segments
   int32_t max_bucket = -1;             // largest length bucket over the segments
   int32_t n_pad = 0;                   // pad rows of the on-chip state (kPadRows when max_bucket > 8)
+  int32_t bucket_table = 0;            // length-bucket table (see bucket_in_table)
   float f_const = 0.f;
   int32_t unit_weights = 1;
 

@@ -38,7 +38,7 @@ class PclsError(RuntimeError):
 
 class PlanOptions(ctypes.Structure):
     _fields_ = [("force_generic", ctypes.c_int32), ("accumulator_bits", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 6)]
+                ("bucket_table", ctypes.c_int32), ("reserved", ctypes.c_int32 * 5)]
 
 
 class StepOptions(ctypes.Structure):
@@ -53,7 +53,7 @@ class Info(ctypes.Structure):
                 ("grad_scale_log2_32", ctypes.c_int32), ("obj_scale_log2", ctypes.c_int32),
                 ("tile_restarts", ctypes.c_int32), ("block_threads", ctypes.c_int32),
                 ("workspace_bytes", ctypes.c_size_t), ("lds_bytes_per_restart", ctypes.c_size_t),
-                ("cons_by_kind", ctypes.c_int32 * 5)]
+                ("cons_by_kind", ctypes.c_int32 * 5), ("bucket_table", ctypes.c_int32)]
 
 KIND_NAMES = ("prod1", "prod2", "dft", "pmf", "const")
 
@@ -136,7 +136,8 @@ def _stream(stream=None):
 class Plan:
     """Host-side plan of a formula (no device memory)."""
 
-    def __init__(self, n, row_ptr, lit, ctype, param=None, weight=None, force_generic=False, accumulator_bits=0):
+    def __init__(self, n, row_ptr, lit, ctype, param=None, weight=None, force_generic=False, accumulator_bits=0,
+                 bucket_table=0):
         L = load_library()
         self.n = int(n)
         self._row_ptr = np.ascontiguousarray(row_ptr, np.int32)
@@ -150,6 +151,7 @@ class Plan:
         opts = PlanOptions()
         opts.force_generic = 1 if force_generic else 0
         opts.accumulator_bits = int(accumulator_bits)
+        opts.bucket_table = int(bucket_table)
         st = L.pcls_plan_ex(self.n, self.m, _ptr(self._row_ptr), _ptr(self._lit), _ptr(self._type),
                             _ptr(self._param), _ptr(self._weight), ctypes.byref(opts), ctypes.byref(h),
                             ctypes.byref(ws))
@@ -158,9 +160,9 @@ class Plan:
         self.workspace_bytes = ws.value
 
     @classmethod
-    def from_instance(cls, inst, force_generic=False, accumulator_bits=0):
+    def from_instance(cls, inst, force_generic=False, accumulator_bits=0, bucket_table=0):
         return cls(inst.n, inst.row_ptr, inst.lit, inst.ctype, inst.param, inst.weight, force_generic,
-                   accumulator_bits)
+                   accumulator_bits, bucket_table)
 
     def info(self) -> Info:
         info = Info()
@@ -195,9 +197,9 @@ class Problem(Plan):
     """A plan bound to a device workspace (a torch uint8 tensor)."""
 
     def __init__(self, n, row_ptr, lit, ctype, param=None, weight=None, force_generic=False, device="cuda",
-                 accumulator_bits=0):
+                 accumulator_bits=0, bucket_table=0):
         import torch
-        super().__init__(n, row_ptr, lit, ctype, param, weight, force_generic, accumulator_bits)
+        super().__init__(n, row_ptr, lit, ctype, param, weight, force_generic, accumulator_bits, bucket_table)
         dev = torch.device(device)
         if dev.type == "cuda" and dev.index is None:
             dev = torch.device("cuda", torch.cuda.current_device())
@@ -209,9 +211,9 @@ class Problem(Plan):
                                           _stream()))
 
     @classmethod
-    def from_instance(cls, inst, force_generic=False, device="cuda", accumulator_bits=0):
+    def from_instance(cls, inst, force_generic=False, device="cuda", accumulator_bits=0, bucket_table=0):
         return cls(inst.n, inst.row_ptr, inst.lit, inst.ctype, inst.param, inst.weight, force_generic, device,
-                   accumulator_bits)
+                   accumulator_bits, bucket_table)
 
     # ---- state
     def new_state(self, R: int):

@@ -170,3 +170,25 @@ def test_plan_picks_evaluation_path(k):
             counts = dict(zip(pcls.KIND_NAMES, pcls.Plan.from_instance(inst).info().cons_by_kind))
             want = _expected_kind(list(C.spectrum(ctype, k, prm)))
             assert counts[want] == 1, (C.TYPE_NAMES[ctype], k, prm, counts, want)
+
+
+def test_bucket_tables():
+    """Table 1 pads lengths above 8 to powers of two only: fewer or equal
+    segments, the same evaluation kinds for the short constraints; the table is
+    reported and an unknown table is refused."""
+    inst = synth.mixed_small(n=120, seed=4, kmax=40, count=300)
+    p0 = pcls.Plan.from_instance(inst)
+    p1 = pcls.Plan.from_instance(inst, bucket_table=1)
+    assert p0.info().bucket_table == 0 and p1.info().bucket_table == 1
+    assert p1.info().n_segments <= p0.info().n_segments
+    assert p0.info().n_cons == p1.info().n_cons == inst.m
+    with pytest.raises(pcls.PclsError) as e:
+        pcls.Plan.from_instance(inst, bucket_table=2)
+    assert e.value.status == pcls.PCLS_E_INVALID
+    # a 12-literal threshold: count window of 6 fits the 12 bucket (table 0) and the 16 bucket (table 1)
+    k = 12
+    one = synth.Instance(n=k, row_ptr=np.array([0, k], np.int32), lit=np.arange(1, k + 1, dtype=np.int32),
+                         ctype=np.array([synth.CARD_GE], np.int8), param=np.array([6], np.int32))
+    for t in (0, 1):
+        counts = dict(zip(pcls.KIND_NAMES, pcls.Plan.from_instance(one, bucket_table=t).info().cons_by_kind))
+        assert counts["pmf"] == 1
