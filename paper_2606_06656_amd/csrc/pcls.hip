@@ -278,8 +278,11 @@ __device__ __forceinline__ void fetch_pair(const ProblemDev& P, const Segment& S
 __device__ __forceinline__ unsigned lit_off(int code, int logT, int t) {
   return ((unsigned)code << (logT + 2)) | ((unsigned)t << 2);
 }
-__device__ __forceinline__ float x_at(const float* xs, unsigned off) {
-  return *reinterpret_cast<const float*>(reinterpret_cast<const char*>(xs) + off);
+// x is the first array of the kernels' dynamic LDS, which starts at LDS
+// address 0 (the kernels hold no static LDS; the host checks this), so the
+// byte offset is the address itself: no base add per literal.
+__device__ __forceinline__ float x_at(const float*, unsigned off) {
+  return *reinterpret_cast<const __attribute__((address_space(3))) float*>((size_t)off);
 }
 template <class AT>
 __device__ __forceinline__ AT* g_at(AT* gs, unsigned off) {
@@ -1603,13 +1606,15 @@ __device__ __forceinline__ ProblemDev load_problem(kptr<BatchInst> bi) {
 template <int MAXB, class AT>
 __global__ void __launch_bounds__(1024) batch_kernel(const BatchInst* __restrict__ insts,
                                                      const BatchItem* __restrict__ items, int n_items,
-                                                     unsigned int* __restrict__ counter, float lr, int n_steps) {
+                                                     unsigned int* __restrict__ counter, float lr, int n_steps,
+                                                     int claim_off) {
   extern __shared__ __attribute__((aligned(16))) unsigned long long lds_raw[];  // 16 B: vector LDS accesses
-  __shared__ int claimed;
+  // the claimed item's word sits after the largest tile (no static LDS)
+  int* claimed = reinterpret_cast<int*>(reinterpret_cast<char*>(lds_raw) + claim_off);
   for (;;) {
-    if (threadIdx.x == 0) claimed = (int)atomicAdd(counter, 1u);
+    if (threadIdx.x == 0) *claimed = (int)atomicAdd(counter, 1u);
     __syncthreads();
-    const int it = claimed;
+    const int it = *claimed;
     __syncthreads();
     if (it >= n_items) break;  // every workgroup reaches this once the list is drained
     kptr<BatchItem> W = kconst(items) + it;
@@ -1767,6 +1772,15 @@ struct DeviceLimits {
 std::mutex g_dev_mu;
 DeviceLimits g_dev[64];
 
+// The literal gathers address x by its LDS byte offset alone, which holds only
+// while a kernel's dynamic LDS starts at address 0: no static LDS.
+hipError_t check_no_static_lds(const void* f) {
+  hipFuncAttributes a{};
+  hipError_t e = hipFuncGetAttributes(&a, f);
+  if (e != hipSuccess) return e;
+  return a.sharedSizeBytes == 0 ? hipSuccess : hipErrorInvalidKernelFile;
+}
+
 int32_t device_limits(DeviceLimits& out) {
   int dev = 0;
   PCLS_HIP(hipGetDevice(&dev), "hipGetDevice");
@@ -1790,8 +1804,10 @@ int32_t device_limits(DeviceLimits& out) {
                               (const void*)stats_kernel<kMaxbShort>,
                               (const void*)stats_kernel<kMaxbMid>,
                               (const void*)stats_kernel<kMaxbAll>};
-    for (const void* f : variants)
+    for (const void* f : variants) {
       PCLS_HIP(hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, d.lds_max), "hipFuncSetAttribute");
+      PCLS_HIP(check_no_static_lds(f), "kernel attributes");
+    }
     d.lds_attr_set = true;
   }
   out = d;
@@ -1974,7 +1990,7 @@ int32_t batch_configure(BatchState& b, const pcls_batch_config& cfg_in, hipStrea
   if (cfg.block_threads == 0) cfg.block_threads = 1024;
   if (cfg.block_threads != 256 && cfg.block_threads != 512 && cfg.block_threads != 1024)
     return set_error(PCLS_E_INVALID, "block_threads %d must be 256, 512 or 1024", cfg.block_threads);
-  // the persistent kernel keeps one claimed-item word in static LDS beside the tiles
+  // the persistent kernel keeps one claimed-item word after the tiles
   const int lds_cap = lim.lds_max - 256;
   if (cfg.lds_budget <= 0 || cfg.lds_budget > lds_cap) cfg.lds_budget = lds_cap;
   if (cfg.accumulator_bits != 0 && cfg.accumulator_bits != 32 && cfg.accumulator_bits != 64)
@@ -2076,11 +2092,13 @@ int32_t batch_launch(BatchState& b, float lr, int n_steps, hipStream_t stream) {
   if (b.acc64) {
     auto k = b.maxb <= kMaxbShort ? batch_kernel<kMaxbShort, unsigned long long>
                          : (b.maxb <= kMaxbMid ? batch_kernel<kMaxbMid, unsigned long long> : batch_kernel<kMaxbAll, unsigned long long>);
-    hipLaunchKernelGGL(k, grid, block, b.lds, stream, insts, items, b.n_items, counter, lr, n_steps);
+    hipLaunchKernelGGL(k, grid, block, b.lds + 256, stream, insts, items, b.n_items, counter, lr, n_steps,
+                       (int)b.lds);
   } else {
     auto k = b.maxb <= kMaxbShort ? batch_kernel<kMaxbShort, unsigned int>
                          : (b.maxb <= kMaxbMid ? batch_kernel<kMaxbMid, unsigned int> : batch_kernel<kMaxbAll, unsigned int>);
-    hipLaunchKernelGGL(k, grid, block, b.lds, stream, insts, items, b.n_items, counter, lr, n_steps);
+    hipLaunchKernelGGL(k, grid, block, b.lds + 256, stream, insts, items, b.n_items, counter, lr, n_steps,
+                       (int)b.lds);
   }
   PCLS_HIP(hipGetLastError(), "batch_kernel launch");
   return PCLS_OK;
@@ -2100,10 +2118,11 @@ int32_t batch_attrs() {
     const void* fs[] = {(const void*)batch_kernel<kMaxbShort, unsigned long long>, (const void*)batch_kernel<kMaxbMid, unsigned long long>,
                         (const void*)batch_kernel<kMaxbAll, unsigned long long>, (const void*)batch_kernel<kMaxbShort, unsigned int>,
                         (const void*)batch_kernel<kMaxbMid, unsigned int>, (const void*)batch_kernel<kMaxbAll, unsigned int>};
-    // the kernel's static LDS word sits beside the dynamic tiles
-    for (const void* f : fs)
-      PCLS_HIP(hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, lim.lds_max - 256),
+    for (const void* f : fs) {
+      PCLS_HIP(hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, lim.lds_max),
                "hipFuncSetAttribute");
+      PCLS_HIP(check_no_static_lds(f), "batch kernel attributes");
+    }
     g_batch_attr_set[dev] = true;
   }
   return PCLS_OK;
