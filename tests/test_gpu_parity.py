@@ -378,17 +378,18 @@ def test_short_types_two_restart_lanes(T):
     assert torch.equal(X1[:, :R], X2[:, :R])
 
 
-@pytest.mark.parametrize("T,kmax", [(2, 256), (4, 128), (8, 64)])
+@pytest.mark.parametrize("T,kmax", [(2, 256), (4, 128), (8, 64), (8, 32)])
 def test_long_types_lane_groups_across_tile_widths(T, kmax):
-    """Constraints spread over groups of up to 32 lanes (DFT and long products):
-    at tile widths T >= 2 the group scans run as wave shuffles, at T = 1 as row
-    shifts inside 16-lane rows.  Both agree with the oracle and give bitwise
-    equal gradients and iterates.  (T times the group width must fit one wave.)"""
+    """Constraints spread over groups of up to 32 lanes (DFT, long products and
+    the count windows of 9 to 48 literals): at tile widths T >= 2 the group scans
+    and exchanges run as wave shuffles, at T = 1 as DPP moves inside 16-lane
+    rows.  Both agree with the oracle and give bitwise equal gradients and
+    iterates.  (T times the group width must fit one wave.)"""
     inst = synth.mixed_small(n=300, seed=41, kmax=kmax, count=120)
     log(f"case long types T={T} m={inst.m} L={inst.L}")
     prob = pcls.Problem.from_instance(inst)
     kinds = dict(zip(pcls.KIND_NAMES, prob.info().cons_by_kind))
-    assert kinds["dft"] > 0 and kinds["prod1"] > 0
+    assert kinds["prod1"] > 0 and kinds["dft"] + kinds["pmf"] > 0
     R = 64
     x = corner_mix(np.random.default_rng(41), R, inst.n)
     X = prob.state_from_rows(x)
