@@ -169,20 +169,49 @@ def test_c2_sampled_steps():
 
 
 def test_c3_full_size_sampled():
-    """Long-support n=20000, m=40000, R=4096 evaluated at full size; 3 sampled restarts."""
+    """Long-support n=20000, m=40000, R=4096 at full size, in the launch shape the
+    benchmark times (automatic tile, 10-step launches): 9 steps, then a 1-step
+    launch with the objective trace.  On 64 sampled restarts: the objective and
+    gradient at the 9th iterate against the oracle, the trace row (the stepping
+    kernel's objective at that iterate) equal to the evaluated one, and the 10th
+    iterate against clip(x - lr g_oracle).
+
+    Besides the mixed bound, the objective is held to a bound for a sum of m
+    terms whose errors are each at most TOL (the single-constraint parity bound),
+    of either sign and independent between constraints (separate FP32
+    computations, each rounded to nearest into the fixed-point sum): by
+    Hoeffding's inequality |dF| <= TOL sqrt(2 sum_c w_c^2 ln(2/delta)) except
+    with probability delta = 1e-9, about 1/30 of the worst case TOL sum_c |w_c|."""
     inst = synth.c3_long()
     log(f"case c3 L={inst.L}")
     prob = pcls.Problem.from_instance(inst)
-    R = 4096
+    R, lr = 4096, 0.1
     X = prob.new_state(R)
     prob.init_restarts(X, R, 3)
-    prob.step(X, R, 0.1, 2)
-    obj, grad = prob.evaluate(X, R)
-    sample = np.array([0, 1777, 4095])
-    xt = rows_of(X, R)[sample]
-    ref = oracle_for(inst, with_coefficients=False).evaluate(xt, method=N.PMF)
+    prob.step(X, R, lr, 9)
+    X9 = X.clone()
+    tr = prob.step(X, R, lr, 1, trace=True)
+    obj, grad = prob.evaluate(X9, R)
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(17)
+    sample = np.unique(np.concatenate([[0, 1, 2047, 4095], rng.choice(R, 60, replace=False)]))
+    x9 = rows_of(X9, R)[sample]
+    ref = oracle_for(inst, with_coefficients=False).evaluate(x9, method=N.PMF)
+    o = obj.cpu().numpy()[sample]
     g = grad[:, :R].T.cpu().numpy()[sample]
-    assert_obj_grad(obj.cpu().numpy()[sample], g, ref, what="c3", inst=inst)
+    assert_obj_grad(o, g, ref, what="c3", inst=inst)
+    w = np.ones(inst.m) if inst.weight is None else np.asarray(inst.weight, np.float64)
+    hoeff = TOL * np.sqrt(2.0 * np.sum(w * w) * np.log(2.0 / 1e-9))
+    err = np.abs(o.astype(np.float64) - ref["obj"])
+    assert err.max() <= hoeff, (err.max(), hoeff)
+    # the stepping kernel's objective at the same iterate is the same fixed-point sum
+    assert np.array_equal(tr.cpu().numpy()[0][sample], o)
+    # the step taken from that iterate
+    _, sg = range_scales(inst)
+    x10 = rows_of(X, R)[sample]
+    expect = np.clip(x9 - lr * ref["grad"], -1, 1)
+    slack = lr * TOL * np.maximum(np.abs(ref["grad"]), sg) + 2.0 ** -22
+    assert np.all(np.abs(x10 - expect) <= slack)
 
 
 def test_c3_forced_long():
