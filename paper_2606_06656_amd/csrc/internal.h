@@ -44,9 +44,10 @@ constexpr int kMaxSegments = 4 * kNumBuckets;  // (kind, bucket) pairs of the no
 // rows in the on-chip state, held at x = +1 and never stepped.  A slot past a
 // constraint's end (length buckets above 8) codes one of these rows, with the
 // literal sign chosen so that the slot's factor is exactly 1 (its gradient
-// term lands in the pad row, whose accumulator is never read).  Constraint q
-// of a segment uses pad row q mod kPadRows, so the lanes of one instruction
-// hit different rows.
+// term lands in the pad row, whose accumulator is never read).  Slot i of
+// constraint q of a segment starts on pad row (q + i) mod kPadRows, so pads
+// spread over banks; the planner's bank balance may then move them between
+// the constraint's slots.
 constexpr int kPadRows = 64;
 
 // Lanes per (constraint, restart) pair: one lane holds up to 16 literals of a

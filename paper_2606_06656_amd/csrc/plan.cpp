@@ -121,6 +121,54 @@ static void bank_aware_order(const int32_t* row_ptr, const int32_t* lit, int k, 
   std::copy(out.begin(), out.end(), run);
 }
 
+// LDS bank balance of the long buckets.  One wave instruction of the
+// long-constraint kernels reads slot lig*J + j (J = kmax/G) of every lane group
+// of a chunk; with one restart per tile that is the 64/G constraints of the
+// chunk on G lanes each, and x of variable v (and its gradient accumulator)
+// sits in LDS bank v mod 64.  A symmetric constraint's literals and pad slots
+// may take any of its slots, so moving one between instructions j1 != j2 of
+// its own constraint changes no value.  A local search swaps slot pairs of one
+// constraint while that lowers the sum over the chunk's instructions of the
+// squared bank counts.  seg: the segment's transposed codes [slot][c_count].
+static void balance_long_slots(int32_t* seg, int c_count, int kmax, int G) {
+  const int J = kmax / G, chunk = 64 / G;
+  std::vector<int> cnt((size_t)J * 64);
+  auto bank = [](int32_t code) { return (int)((uint32_t)code & 0x7fffffffu) & 63; };
+  for (int c0 = 0; c0 < c_count; c0 += chunk) {
+    const int c1 = std::min(c_count, c0 + chunk);
+    std::fill(cnt.begin(), cnt.end(), 0);
+    for (int q = c0; q < c1; ++q)
+      for (int s = 0; s < kmax; ++s) ++cnt[(size_t)(s % J) * 64 + bank(seg[(size_t)s * c_count + q])];
+    for (int pass = 0; pass < 4; ++pass) {
+      bool changed = false;
+      for (int q = c0; q < c1; ++q) {
+        for (int s1 = 0; s1 < kmax; ++s1) {
+          for (int s2 = s1 + 1; s2 < kmax; ++s2) {
+            const int j1 = s1 % J, j2 = s2 % J;
+            if (j1 == j2) continue;
+            int32_t& a = seg[(size_t)s1 * c_count + q];
+            int32_t& b = seg[(size_t)s2 * c_count + q];
+            const int b1 = bank(a), b2 = bank(b);
+            if (b1 == b2) continue;
+            // a moves j1 -> j2, b moves j2 -> j1: change of the sum of squares
+            const int d = 2 * (cnt[(size_t)j2 * 64 + b1] - cnt[(size_t)j1 * 64 + b1] + 1) +
+                          2 * (cnt[(size_t)j1 * 64 + b2] - cnt[(size_t)j2 * 64 + b2] + 1);
+            if (d < 0) {
+              --cnt[(size_t)j1 * 64 + b1];
+              ++cnt[(size_t)j2 * 64 + b1];
+              --cnt[(size_t)j2 * 64 + b2];
+              ++cnt[(size_t)j1 * 64 + b2];
+              std::swap(a, b);
+              changed = true;
+            }
+          }
+        }
+      }
+      if (!changed) break;
+    }
+  }
+}
+
 static void classify(const std::vector<int>& sp, bool force_generic, int table, ClassRec& C) {
   const int k = (int)sp.size() - 1;
   bool all_eq = true, tail_eq = true, head_eq = true, alt = true, mid_eq = true;
@@ -520,10 +568,12 @@ int32_t build_plan(int32_t n, int32_t m, const int32_t* row_ptr, const int32_t* 
       // (1 - y)/2 and for counts of false literals (h < 0), y = +1 otherwise
       const ClassRec& C = P->classes[P->c_cls[cj]];
       const bool neg = (C.kind == KIND_PROD1 && C.b < 0.f) || (C.kind == KIND_PMF && (C.k > kPmfMaxK && pmf_counts_false_of(P->nodes, C)));
-      const uint32_t pad = (uint32_t)(n + q % kPadRows) | (neg ? 0x80000000u : 0u);
-      for (int i = P->c_k[cj]; i < kmax; ++i) P->litT[(size_t)S.lit_base + (size_t)i * S.c_count + q] = (int32_t)pad;
+      for (int i = P->c_k[cj]; i < kmax; ++i)
+        P->litT[(size_t)S.lit_base + (size_t)i * S.c_count + q] =
+            (int32_t)((uint32_t)(n + (q + i) % kPadRows) | (neg ? 0x80000000u : 0u));
     }
     const int G = group_size(S.kind, kmax);
+    if (kmax > 8) balance_long_slots(P->litT.data() + S.lit_base, S.c_count, kmax, G);
     P->max_group = std::max(P->max_group, G);
     P->max_bucket = std::max(P->max_bucket, b);
     P->segments.push_back(S);
