@@ -97,13 +97,10 @@ __device__ __forceinline__ long long fixed_term(float v) {
   return __double_as_longlong((double)v + 6755399441055744.0) - 0x4338000000000000LL;
 }
 
-// ---------------------------------------------------------------- group scans
-// Exclusive prefix / suffix products of one value per lane over the G lanes of
-// one (constraint, restart) pair (Hillis-Steele, log2 G steps).  A pair's G
-// lanes sit at stride T inside the wave (lane = t + T * (lig + G * sub)).  With T = 1 and G <= 16 a group lies inside one
-// 16-lane row, and each scan step is a DPP row shift (one VALU move, no LDS);
-// otherwise the steps are wave shuffles.  Both paths multiply in the same order,
-// so the results are identical bit for bit.
+// ---------------------------------------------------------------- lane groups
+// A pair's G lanes sit at stride T inside the wave (lane = t + T * (lig + G * sub));
+// with T = 1 and G <= 16 a group lies inside one 16-lane row, where DPP row
+// operations reach its lanes (one VALU move, no LDS traffic).
 template <int D>
 __device__ __forceinline__ float row_shr(float v) {  // lane l reads lane l - D of its row
   return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x110 + D, 0xf, 0xf, true));
@@ -113,129 +110,57 @@ __device__ __forceinline__ float row_shl(float v) {  // lane l reads lane l + D 
   return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x100 + D, 0xf, 0xf, true));
 }
 
-template <int G, int D = 1>
-__device__ __forceinline__ void prefix_steps_dpp(float& inc, int lig) {
-  if constexpr (D < G) {
-    const float o = row_shr<D>(inc);
-    if (lig >= D) inc *= o;
-    prefix_steps_dpp<G, 2 * D>(inc, lig);
+// Leave-one-out product over a pair's G lanes: the product of the values of the
+// other G - 1 lanes, by a butterfly of lane exchanges (log2 G levels; at level
+// D a lane multiplies in the total of the block of D lanes at xor distance D,
+// and both blocks' lanes form their union's total).  The exchanges reach the
+// same partner lane at every tile width, so the result does not depend on T.
+// With T = 1: distances 1 and 2 are DPP quad permutations, 4 two row shifts and
+// a select, 8 a row rotation; 16 and every distance at T > 1 are wave shuffles.
+template <int D>
+__device__ __forceinline__ float grp_xchg(float v, int lig, int T) {
+  if (T == 1) {
+    if constexpr (D == 1) return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0xB1, 0xf, 0xf, true));
+    if constexpr (D == 2) return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x4E, 0xf, 0xf, true));
+    if constexpr (D == 4) {
+      const float up = row_shl<4>(v), dn = row_shr<4>(v);
+      return (lig & 4) ? dn : up;
+    }
+    if constexpr (D == 8) return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x128, 0xf, 0xf, true));
   }
-}
-template <int G, int D = 1>
-__device__ __forceinline__ void suffix_steps_dpp(float& inc, int lig) {
-  if constexpr (D < G) {
-    const float o = row_shl<D>(inc);
-    if (lig + D < G) inc *= o;
-    suffix_steps_dpp<G, 2 * D>(inc, lig);
-  }
-}
-template <int G, int D = 1>
-__device__ __forceinline__ void prefix_steps_dpp_c(cf& inc, int lig) {
-  if constexpr (D < G) {
-    const cf o{row_shr<D>(inc.r), row_shr<D>(inc.i)};
-    if (lig >= D) inc = cmul(o, inc);
-    prefix_steps_dpp_c<G, 2 * D>(inc, lig);
-  }
-}
-template <int G, int D = 1>
-__device__ __forceinline__ void suffix_steps_dpp_c(cf& inc, int lig) {
-  if constexpr (D < G) {
-    const cf o{row_shl<D>(inc.r), row_shl<D>(inc.i)};
-    if (lig + D < G) inc = cmul(inc, o);
-    suffix_steps_dpp_c<G, 2 * D>(inc, lig);
-  }
+  return __shfl_xor(v, D * T);
 }
 
-template <int G>
-__device__ __forceinline__ float grp_prefix(float v, int lig, int T) {
-  if constexpr (G == 1) {
-    return 1.f;
-  } else {
-    float inc = v;
-    if constexpr (G <= 16) {
-      if (T == 1) {
-        prefix_steps_dpp<G>(inc, lig);
-        const float ex = row_shr<1>(inc);
-        return lig == 0 ? 1.f : ex;
-      }
-    }
-#pragma unroll
-    for (int d = 1; d < G; d <<= 1) {
-      float o = __shfl_up(inc, d * T);
-      if (lig >= d) inc *= o;
-    }
-    float ex = __shfl_up(inc, T);
-    return lig == 0 ? 1.f : ex;
+template <int G, int D = 1>
+__device__ __forceinline__ void excl_levels(float& ex, float& tot, int lig, int T) {
+  if constexpr (D < G) {
+    const float o = grp_xchg<D>(tot, lig, T);
+    ex *= o;
+    if constexpr (2 * D < G) tot *= o;
+    excl_levels<G, 2 * D>(ex, tot, lig, T);
   }
 }
-
 template <int G>
-__device__ __forceinline__ float grp_suffix(float v, int lig, int T) {
-  if constexpr (G == 1) {
-    return 1.f;
-  } else {
-    float inc = v;
-    if constexpr (G <= 16) {
-      if (T == 1) {
-        suffix_steps_dpp<G>(inc, lig);
-        const float ex = row_shl<1>(inc);
-        return lig == G - 1 ? 1.f : ex;
-      }
-    }
-#pragma unroll
-    for (int d = 1; d < G; d <<= 1) {
-      float o = __shfl_down(inc, d * T);
-      if (lig + d < G) inc *= o;
-    }
-    float ex = __shfl_down(inc, T);
-    return lig == G - 1 ? 1.f : ex;
-  }
+__device__ __forceinline__ float grp_excl(float v, int lig, int T) {
+  float ex = 1.f, tot = v;
+  excl_levels<G>(ex, tot, lig, T);
+  return ex;
 }
 
-template <int G>
-__device__ __forceinline__ cf grp_prefix_c(cf v, int lig, int T) {
-  if constexpr (G == 1) {
-    return {1.f, 0.f};
-  } else {
-    cf inc = v;
-    if constexpr (G <= 16) {
-      if (T == 1) {
-        prefix_steps_dpp_c<G>(inc, lig);
-        const cf ex{row_shr<1>(inc.r), row_shr<1>(inc.i)};
-        return lig == 0 ? cf{1.f, 0.f} : ex;
-      }
-    }
-#pragma unroll
-    for (int d = 1; d < G; d <<= 1) {
-      cf o{__shfl_up(inc.r, d * T), __shfl_up(inc.i, d * T)};
-      if (lig >= d) inc = cmul(o, inc);
-    }
-    cf ex{__shfl_up(inc.r, T), __shfl_up(inc.i, T)};
-    return lig == 0 ? cf{1.f, 0.f} : ex;
+template <int G, int D = 1>
+__device__ __forceinline__ void excl_levels_c(cf& ex, cf& tot, int lig, int T) {
+  if constexpr (D < G) {
+    const cf o{grp_xchg<D>(tot.r, lig, T), grp_xchg<D>(tot.i, lig, T)};
+    ex = cmul(ex, o);
+    if constexpr (2 * D < G) tot = cmul(tot, o);
+    excl_levels_c<G, 2 * D>(ex, tot, lig, T);
   }
 }
-
 template <int G>
-__device__ __forceinline__ cf grp_suffix_c(cf v, int lig, int T) {
-  if constexpr (G == 1) {
-    return {1.f, 0.f};
-  } else {
-    cf inc = v;
-    if constexpr (G <= 16) {
-      if (T == 1) {
-        suffix_steps_dpp_c<G>(inc, lig);
-        const cf ex{row_shl<1>(inc.r), row_shl<1>(inc.i)};
-        return lig == G - 1 ? cf{1.f, 0.f} : ex;
-      }
-    }
-#pragma unroll
-    for (int d = 1; d < G; d <<= 1) {
-      cf o{__shfl_down(inc.r, d * T), __shfl_down(inc.i, d * T)};
-      if (lig + d < G) inc = cmul(inc, o);
-    }
-    cf ex{__shfl_down(inc.r, T), __shfl_down(inc.i, T)};
-    return lig == G - 1 ? cf{1.f, 0.f} : ex;
-  }
+__device__ __forceinline__ cf grp_excl_c(cf v, int lig, int T) {
+  cf ex{1.f, 0.f}, tot = v;
+  excl_levels_c<G>(ex, tot, lig, T);
+  return ex;
 }
 
 // ------------------------------------------------------ one constraint, one restart
@@ -365,20 +290,18 @@ __device__ __forceinline__ void prod_pair(const Fetched<KMAX / G>& fp, int lig, 
       run2 *= f2[j];
     }
   }
-  const float xp1 = grp_prefix<G>(run1, lig, T), xq1 = grp_suffix<G>(run1, lig, T);
-  float xp2 = 1.f, xq2 = 1.f;
-  if constexpr (NN == 2) {
-    xp2 = grp_prefix<G>(run2, lig, T);
-    xq2 = grp_suffix<G>(run2, lig, T);
-  }
+  // the other lanes' products
+  const float ex1 = grp_excl<G>(run1, lig, T);
+  float ex2 = 1.f;
+  if constexpr (NN == 2) ex2 = grp_excl<G>(run2, lig, T);
   if (lig == 0) {
-    float fe = c1 * (run1 * xq1);
-    if constexpr (NN == 2) fe = fmaf(c2, run2 * xq2, fe);
+    float fe = c1 * (run1 * ex1);
+    if constexpr (NN == 2) fe = fmaf(c2, run2 * ex2, fe);
     fchunk = fmaf(fp.w * fsc, fe, fchunk);
   }
-  const float s1 = c1 * b1 * (fp.w * gsc) * xp1;
-  const float s2 = -0.5f * c2 * (fp.w * gsc) * xp2;
-  float suf1 = xq1, suf2 = xq2;
+  const float s1 = c1 * b1 * (fp.w * gsc) * ex1;
+  const float s2 = -0.5f * c2 * (fp.w * gsc) * ex2;
+  float suf1 = 1.f, suf2 = 1.f;
 #pragma unroll
   for (int j = J - 1; j >= 0; --j) {
     float g = s1 * pre1[j] * suf1;
@@ -426,10 +349,10 @@ __device__ __forceinline__ void dft_pair(const ProblemDev& P, int m_max, int cls
       pre[j] = run;
       run *= y[j];
     }
-    const float xp = grp_prefix<G>(run, lig, T), xq = grp_suffix<G>(run, lig, T);
-    fe = cn * (run * xq);
-    const float sc = cn * xp;
-    float suf = xq;
+    const float ex = grp_excl<G>(run, lig, T);
+    fe = cn * (run * ex);
+    const float sc = cn * ex;
+    float suf = 1.f;
 #pragma unroll
     for (int j = J - 1; j >= 0; --j) {
       g[j] = sc * pre[j] * suf;
@@ -448,14 +371,13 @@ __device__ __forceinline__ void dft_pair(const ProblemDev& P, int m_max, int cls
         const cf f{fmaf(N.br, y[j], N.ar), fmaf(N.bi, y[j], N.ai)};
         run = cmul(run, f);
       }
-      const cf xp = grp_prefix_c<G>(run, lig, T);
-      const cf xq = grp_suffix_c<G>(run, lig, T);
-      const cf tot = cmul(run, xq);
+      const cf ex = grp_excl_c<G>(run, lig, T);  // the other lanes' node products
+      const cf tot = cmul(run, ex);
       fe = fmaf(N.wr, tot.r, fmaf(-N.wi, tot.i, fe));
       // The gradient of literal j is Re(gw * prefix_j * suffix_j), gw the node's
-      // gradient weight: carrying S_j = gw * (group prefix) * suffix_j down the
-      // literals leaves one real part of a product per literal.
-      cf S = cmul(cmul(cf{N.gr, N.gi}, xp), xq);
+      // gradient weight: carrying S_j = gw * (other lanes) * (lane suffix)_j down
+      // the literals leaves one real part of a product per literal.
+      cf S = cmul(cf{N.gr, N.gi}, ex);
 #pragma unroll
       for (int j = J - 1; j >= 0; --j) {
         g[j] = fmaf(pre[j].r, S.r, fmaf(-pre[j].i, S.i, g[j]));  // Re(pre_j * S_j)
