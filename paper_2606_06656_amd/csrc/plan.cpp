@@ -129,7 +129,10 @@ static void bank_aware_order(const int32_t* row_ptr, const int32_t* lit, int k, 
 // may take any of its slots, so moving one between instructions j1 != j2 of
 // its own constraint changes no value.  A local search swaps slot pairs of one
 // constraint while that lowers the sum over the chunk's instructions of the
-// squared bank counts.  seg: the segment's transposed codes [slot][c_count].
+// squared bank counts (two passes over each constraint's slot pairs: planning
+// work O(L kmax), so the search stops at the 64 bucket; from 96 literals a
+// chunk holds at most 4 constraints and the gathers are few per literal).
+// seg: the segment's transposed codes [slot][c_count].
 static void balance_long_slots(int32_t* seg, int c_count, int kmax, int G) {
   const int J = kmax / G, chunk = 64 / G;
   std::vector<int> cnt((size_t)J * 64);
@@ -139,7 +142,7 @@ static void balance_long_slots(int32_t* seg, int c_count, int kmax, int G) {
     std::fill(cnt.begin(), cnt.end(), 0);
     for (int q = c0; q < c1; ++q)
       for (int s = 0; s < kmax; ++s) ++cnt[(size_t)(s % J) * 64 + bank(seg[(size_t)s * c_count + q])];
-    for (int pass = 0; pass < 4; ++pass) {
+    for (int pass = 0; pass < 2; ++pass) {
       bool changed = false;
       for (int q = c0; q < c1; ++q) {
         for (int s1 = 0; s1 < kmax; ++s1) {
@@ -573,7 +576,7 @@ int32_t build_plan(int32_t n, int32_t m, const int32_t* row_ptr, const int32_t* 
             (int32_t)((uint32_t)(n + (q + i) % kPadRows) | (neg ? 0x80000000u : 0u));
     }
     const int G = group_size(S.kind, kmax);
-    if (kmax > 8) balance_long_slots(P->litT.data() + S.lit_base, S.c_count, kmax, G);
+    if (kmax > 8 && kmax <= 64) balance_long_slots(P->litT.data() + S.lit_base, S.c_count, kmax, G);
     P->max_group = std::max(P->max_group, G);
     P->max_bucket = std::max(P->max_bucket, b);
     P->segments.push_back(S);
