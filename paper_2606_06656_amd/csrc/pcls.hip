@@ -299,15 +299,16 @@ __device__ __forceinline__ void prod_pair(const Fetched<KMAX / G>& fp, int lig, 
     if constexpr (NN == 2) fe = fmaf(c2, run2 * ex2, fe);
     fchunk = fmaf(fp.w * fsc, fe, fchunk);
   }
-  const float s1 = c1 * b1 * (fp.w * gsc) * ex1;
-  const float s2 = -0.5f * c2 * (fp.w * gsc) * ex2;
-  float suf1 = 1.f, suf2 = 1.f;
+  // the suffix products start at the gradient scales, so each literal's term
+  // is one product: prefix_j * (scale * suffix_j)
+  float suf1 = c1 * b1 * (fp.w * gsc) * ex1;
+  float suf2 = -0.5f * c2 * (fp.w * gsc) * ex2;
 #pragma unroll
   for (int j = J - 1; j >= 0; --j) {
-    float g = s1 * pre1[j] * suf1;
+    float g = pre1[j] * suf1;
     suf1 *= f1[j];
     if constexpr (NN == 2) {
-      g = fmaf(s2 * pre2[j], suf2, g);
+      g = fmaf(pre2[j], suf2, g);
       suf2 *= f2[j];
     }
     sink.add(el[j], flip(g, lit_sign(fp.code[j])), fp.code[j]);
@@ -845,8 +846,8 @@ __device__ __forceinline__ void prod_pair_r2(const Fetched<KMAX>& fp, int t2, in
   const float a1 = pc.a, b1 = pc.b;
   unsigned el[J];
   float fa1[J], fb1[J], fa2[J], fb2[J];
-  // the literal's sign goes onto the node coefficient (and below onto the
-  // gradient scale) once for both restarts: b (s x) = (s b) x exactly
+  // the literal's sign goes onto the node coefficient once for both restarts:
+  // b (s x) = (s b) x exactly (and below onto each gradient term)
 #pragma unroll
   for (int j = 0; j < J; ++j) {
     el[j] = lit_off(fp.code[j], logT, 2 * t2);
@@ -896,24 +897,23 @@ __device__ __forceinline__ void prod_pair_r2(const Fetched<KMAX>& fp, int t2, in
     s1 *= fp.w;
     s2 *= fp.w;
   }
-  float sa1 = 1.f, sb1 = 1.f, sa2 = 1.f, sb2 = 1.f;
+  // the suffix products start at the gradient scales (one product per term)
+  float sa1 = s1, sb1 = s1, sa2 = s2, sb2 = s2;
 #pragma unroll
   for (int j = J - 1; j >= 0; --j) {
-    const unsigned sg = lit_sign(fp.code[j]);
-    const float s1j = flip(s1, sg);  // dF/dx = s dF/dy
-    float ga = s1j * pa1[j] * sa1, gb = s1j * pb1[j] * sb1;
+    const unsigned sg = lit_sign(fp.code[j]);  // dF/dx = s dF/dy
+    float ga = pa1[j] * sa1, gb = pb1[j] * sb1;
     sa1 *= fa1[j];
     sb1 *= fb1[j];
     if constexpr (NN == 2) {
-      const float s2j = flip(s2, sg);
-      ga = fmaf(s2j * pa2[j], sa2, ga);
-      gb = fmaf(s2j * pb2[j], sb2, gb);
+      ga = fmaf(pa2[j], sa2, ga);
+      gb = fmaf(pb2[j], sb2, gb);
       sa2 *= fa2[j];
       sb2 *= fb2[j];
     }
     AT* gp = g_at(gs, el[j]);
-    FixedAcc<AT>::add(gp, ga);
-    FixedAcc<AT>::add(gp + 1, gb);
+    FixedAcc<AT>::add(gp, flip(ga, sg));
+    FixedAcc<AT>::add(gp + 1, flip(gb, sg));
   }
 }
 
